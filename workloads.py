@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only describes *inputs*: material constants, geometry
+descriptions, run options and the primaries of each event, generated from
+numpy's seeded generator.  It holds none of the transport arithmetic and
+imports neither the product package nor the oracle; both of those receive
+exactly these arrays.
+
+Workloads (energies MeV, lengths cm):
+
+* ``photon_cube``   -- 10 MeV photons on the +z axis into a 10 cm lead cube
+  (Z=82, rho=11.35); Compton + photoelectric + pair; charged secondaries
+  deposit locally; tracking cut 10 keV.
+* ``calorimeter``   -- electrons at normal incidence on 50 layers of
+  2 mm Pb + 5 mm liquid Ar (40 x 40 cm); full e-/e+/photon physics,
+  production cut 0.7 mm, tracking cut 10 keV.  1 GeV for the FP64 shower,
+  10 GeV for the mixed-precision one.
+* ``barrel``        -- concentric cylinders (5 Si layers of 300 um between
+  r = 4 and 50 cm, 50 Pb/LAr layers over r = 150-200 cm, |z| <= 300 cm) in a
+  uniform 1 T field; mixed e-/e+/photon primaries, log-uniform 1-100 GeV,
+  isotropic in |eta| < 1.5.
+* ``serving``       -- Poisson arrivals of events with 1-500 primaries of
+  mixed species, log-uniform 1-100 GeV, on the calorimeter geometry.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import numpy as np
+
+GAMMA, ELECTRON, POSITRON = 0, 1, 2
+
+# (Z, A [g/mol], density [g/cm^3], mean excitation energy [MeV])
+LEAD = (82.0, 207.2, 11.35, 823.0e-6)
+LIQUID_ARGON = (18.0, 39.948, 1.396, 188.0e-6)
+SILICON = (14.0, 28.0855, 2.33, 173.0e-6)
+
+TRACKING_CUT = 0.01  # 10 keV
+
+
+@dataclasses.dataclass
+class Options:
+    tracking_cut: float = TRACKING_CUT
+    production_cut: float = 0.0  # cm; <= 0: thresholds equal the tracking cut
+    compton: int = 1
+    photoelectric: int = 1
+    pair: int = 1
+    ionisation: int = 1
+    brems: int = 1
+    annihilation: int = 1
+    charged_local: int = 0
+    continuous_loss: int = 1
+    step_alpha: float = 0.2
+    step_rfinal: float = 0.01
+    max_steps: int = 1 << 16
+
+
+@dataclasses.dataclass
+class Geometry:
+    kind: int  # 0 slabs (z planes), 1 cylinders (radii)
+    bounds: np.ndarray  # n_vol + 1 float64
+    material: np.ndarray  # n_vol int32 (-1 vacuum)
+    tally_bin: np.ndarray  # n_vol int32
+    n_bins: int
+    half_x: float = 0.0
+    half_y: float = 0.0
+    half_z: float = 0.0
+    bz: float = 0.0
+    field_tol: float = 1.0e-5
+
+    @property
+    def n_vol(self) -> int:
+        return int(self.material.shape[0])
+
+
+@dataclasses.dataclass
+class Events:
+    """Primaries of a batch of events, rows grouped by event."""
+    event_ids: np.ndarray  # n_events uint32
+    offsets: np.ndarray  # n_events + 1 int64
+    species: np.ndarray  # n_prim int32
+    energy: np.ndarray  # n_prim float64
+    pos: np.ndarray  # n_prim x 3 float64
+    dir: np.ndarray  # n_prim x 3 float64
+    arrival: Optional[np.ndarray] = None  # seconds, serving only
+
+    @property
+    def n_events(self) -> int:
+        return int(self.event_ids.shape[0])
+
+    @property
+    def n_primaries(self) -> int:
+        return int(self.species.shape[0])
+
+    def subset(self, idx) -> "Events":
+        idx = np.asarray(idx, dtype=np.int64)
+        rows = [np.arange(self.offsets[i], self.offsets[i + 1]) for i in idx]
+        rows = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+        counts = self.offsets[idx + 1] - self.offsets[idx]
+        off = np.zeros(len(idx) + 1, np.int64)
+        off[1:] = np.cumsum(counts)
+        return Events(self.event_ids[idx].copy(), off, self.species[rows].copy(),
+                      self.energy[rows].copy(), self.pos[rows].copy(), self.dir[rows].copy(),
+                      None if self.arrival is None else self.arrival[idx].copy())
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    materials: List[tuple]
+    options: Options
+    geometry: Geometry
+    events: Events
+    seed: int
+    note: str = ""
+
+
+def _single_primary_events(n: int, species: int, energy: float, pos, direction,
+                           first_id: int = 0) -> Events:
+    ids = np.arange(first_id, first_id + n, dtype=np.uint32)
+    off = np.arange(n + 1, dtype=np.int64)
+    sp = np.full(n, species, np.int32)
+    en = np.full(n, energy, np.float64)
+    p = np.tile(np.asarray(pos, np.float64), (n, 1))
+    d = np.tile(np.asarray(direction, np.float64), (n, 1))
+    return Events(ids, off, sp, en, p, d)
+
+
+def calorimeter_geometry(n_layers: int = 50, pb: float = 0.2, lar: float = 0.5,
+                         half_xy: float = 20.0) -> Geometry:
+    """Slab stack: layer i is Pb on [i p, i p + pb] then LAr up to (i+1) p, p = pb+lar.
+    Tally bin = volume (Pb of layer i -> 2i, LAr -> 2i+1)."""
+    pitch = pb + lar
+    b = []
+    for i in range(n_layers):
+        b.append(pitch * i)
+        b.append(pitch * i + pb)
+    b.append(pitch * n_layers)
+    bounds = np.array(b, np.float64)
+    mat = np.tile(np.array([0, 1], np.int32), n_layers)
+    bins = np.arange(2 * n_layers, dtype=np.int32)
+    return Geometry(0, bounds, mat, bins, 2 * n_layers, half_x=half_xy, half_y=half_xy)
+
+
+def photon_cube(n_events: int = 10_000, energy: float = 10.0, seed: int = 1) -> Workload:
+    geom = Geometry(0, np.array([-5.0, 5.0]), np.array([0], np.int32), np.array([0], np.int32),
+                    1, half_x=5.0, half_y=5.0)
+    opts = Options(production_cut=0.0, charged_local=1)
+    ev = _single_primary_events(n_events, GAMMA, energy, (0.0, 0.0, -5.0), (0.0, 0.0, 1.0))
+    return Workload("photon_cube", [LEAD], opts, geom, ev, seed,
+                    f"{n_events} x {energy} MeV photons into a 10 cm Pb cube")
+
+
+def calorimeter(n_events: int = 100_000, energy: float = 1000.0, seed: int = 2,
+                first_id: int = 0) -> Workload:
+    geom = calorimeter_geometry()
+    opts = Options(production_cut=0.07)
+    ev = _single_primary_events(n_events, ELECTRON, energy, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0),
+                                first_id)
+    return Workload("calorimeter", [LEAD, LIQUID_ARGON], opts, geom, ev, seed,
+                    f"{n_events} x {energy / 1000:g} GeV e- on 50 x (2 mm Pb + 5 mm LAr)")
+
+
+def barrel_geometry() -> Geometry:
+    """Cylinder shells: vacuum core, 5 Si shells of 0.03 cm at r = 4 + 11.5 i,
+    vacuum to 150 cm, then 50 Pb/LAr layers of 1 cm pitch (0.2857 Pb + 0.7143 LAr)."""
+    b = [0.0]
+    mat = []
+    for i in range(5):
+        r = 4.0 + 11.5 * i
+        mat.append(-1)  # vacuum up to r
+        b.append(r)
+        mat.append(2)  # Si
+        b.append(r + 0.03)
+    mat.append(-1)
+    b.append(150.0)
+    pb = 2.0 / 7.0
+    for i in range(50):
+        r0 = 150.0 + i
+        mat.append(0)
+        b.append(r0 + pb)
+        mat.append(1)
+        b.append(r0 + 1.0)
+    bounds = np.array(b, np.float64)
+    mat = np.array(mat, np.int32)
+    n_vol = mat.shape[0]
+    # bins: each Si shell its own bin, each calorimeter layer (Pb+LAr) one bin, vacuum -> bin 0
+    bins = np.zeros(n_vol, np.int32)
+    nb = 1
+    for j in range(n_vol):
+        if mat[j] == 2:
+            bins[j] = nb
+            nb += 1
+    for j in range(n_vol):
+        if mat[j] in (0, 1):
+            layer = int(round(bounds[j] - 150.0 - 0.5)) if mat[j] == 1 else int(round(bounds[j] - 150.0))
+            bins[j] = nb + layer
+    nb += 50
+    return Geometry(1, bounds, mat, bins, nb, half_z=300.0, bz=1.0, field_tol=1.0e-5)
+
+
+def _log_uniform(rng, n, lo, hi):
+    return np.exp(np.log(lo) + rng.random(n) * np.log(hi / lo))
+
+
+def barrel(n_events: int = 1_000_000, seed: int = 4, source_seed: int = 40) -> Workload:
+    rng = np.random.default_rng(source_seed)
+    n = n_events
+    u = rng.random(n)
+    species = np.where(u < 0.6, ELECTRON, np.where(u < 0.8, POSITRON, GAMMA)).astype(np.int32)
+    energy = _log_uniform(rng, n, 1000.0, 100000.0)
+    cmax = np.tanh(1.5)
+    cost = -cmax + 2.0 * cmax * rng.random(n)
+    phi = 2.0 * np.pi * rng.random(n)
+    sint = np.sqrt(1.0 - cost * cost)
+    d = np.stack([sint * np.cos(phi), sint * np.sin(phi), cost], axis=1)
+    ev = Events(np.arange(n, dtype=np.uint32), np.arange(n + 1, dtype=np.int64), species,
+                energy, np.zeros((n, 3)), d)
+    return Workload("barrel", [LEAD, LIQUID_ARGON, SILICON], Options(production_cut=0.07),
+                    barrel_geometry(), ev, seed,
+                    f"{n} mixed primaries 1-100 GeV, |eta|<1.5, 1 T, cylinders")
+
+
+def serving(n_events: int = 1000, rate_hz: float = 50.0, seed: int = 5,
+            source_seed: int = 50) -> Workload:
+    """Poisson arrivals at `rate_hz`; each event U{1..500} primaries of mixed species
+    (60% e-, 20% e+, 20% photons), log-uniform 1-100 GeV, normal incidence on the
+    calorimeter."""
+    rng = np.random.default_rng(source_seed)
+    counts = rng.integers(1, 501, size=n_events)
+    off = np.zeros(n_events + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    n = int(off[-1])
+    u = rng.random(n)
+    species = np.where(u < 0.6, ELECTRON, np.where(u < 0.8, POSITRON, GAMMA)).astype(np.int32)
+    energy = _log_uniform(rng, n, 1000.0, 100000.0)
+    arrival = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_events))
+    ev = Events(np.arange(n_events, dtype=np.uint32), off, species, energy, np.zeros((n, 3)),
+                np.tile(np.array([0.0, 0.0, 1.0]), (n, 1)), arrival)
+    return Workload("serving", [LEAD, LIQUID_ARGON], Options(production_cut=0.07),
+                    calorimeter_geometry(), ev, seed,
+                    f"{n_events} Poisson events at {rate_hz} Hz, 1-500 primaries")
+
+
+def random_track_states(n: int, n_vol: int, seed: int, e_lo: float = 0.01, e_hi: float = 1.0e5,
+                        species: Optional[np.ndarray] = None, vol_material=None,
+                        bounds=None, half_xy: float = 20.0) -> Dict[str, np.ndarray]:
+    """Random single-step inputs: species, log-uniform energy, a volume, a point
+    inside it (slabs), an isotropic direction, a random key and step count, and
+    interaction lengths left (half of them unset)."""
+    rng = np.random.default_rng(seed)
+    sp = rng.integers(0, 3, n).astype(np.int32) if species is None else species.astype(np.int32)
+    T = _log_uniform(rng, n, e_lo, e_hi)
+    vol = rng.integers(0, n_vol, n).astype(np.int32)
+    if bounds is not None:
+        lo, hi = bounds[vol], bounds[vol + 1]
+        z = lo + (hi - lo) * rng.random(n)
+        # a quarter of the states sit exactly on a boundary plane, entering the volume
+        on = rng.random(n) < 0.25
+        z = np.where(on, lo, z)
+    else:
+        z = rng.random(n)
+    x = (2.0 * rng.random(n) - 1.0) * half_xy
+    y = (2.0 * rng.random(n) - 1.0) * half_xy
+    cost = 2.0 * rng.random(n) - 1.0
+    phi = 2.0 * np.pi * rng.random(n)
+    sint = np.sqrt(1.0 - cost * cost)
+    d = np.stack([sint * np.cos(phi), sint * np.sin(phi), cost], axis=1)
+    if bounds is not None:
+        d[:, 2] = np.where(on, np.abs(d[:, 2]), d[:, 2])
+    nlam = np.where(rng.random(n) < 0.5, -1.0, rng.exponential(1.0, n))
+    key = rng.integers(0, 2**32, size=(n, 3), dtype=np.uint64).astype(np.uint32)
+    nstep = rng.integers(0, 1000, n).astype(np.uint32)
+    return dict(species=sp, energy=T, vol=vol, pos=np.stack([x, y, z], axis=1), dir=d,
+                nlam=nlam, key=key, nstep=nstep, event=np.arange(n, dtype=np.uint32))
