@@ -1,0 +1,322 @@
+"""MI355X electromagnetic-shower step loop -- Python binding of the C ABI.
+
+Argument marshalling only: every step of the transport runs in the HIP kernels
+of ``libemshower.so`` (built in-tree by ``paper_2203_09467_amd/build.py``).
+PyTorch provides device memory (the workspace and the primaries' arrays) and
+the stream.  If the library is missing this module raises at import time;
+there is no CPU fallback.
+
+The functions keep the names of the C entry points (``init_physics_tables``,
+``init_geometry``, ``transport_events``, ``tally_read``); ``Context`` bundles
+them with the workspace a context needs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libemshower.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2203_09467_amd.build")
+
+# One HIP runtime per process: PyTorch loads its own libamdhip64 (SONAME
+# libamdhip64.so.7); importing it first makes this library bind to that same
+# runtime instead of loading a second copy from /opt/rocm.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+EMS_OK, EMS_NOT_READY = 0, 1
+EMS_FP64, EMS_MIXED = 0, 1
+STATUS = {0: "EMS_OK", 1: "EMS_NOT_READY", -1: "EMS_E_ARG", -2: "EMS_E_STATE",
+          -3: "EMS_E_CAPACITY", -4: "EMS_E_HIP", -5: "EMS_E_INTERNAL"}
+NGRID = 200
+
+
+class EmsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.ems_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("pool_capacity", C.c_uint32), ("max_events", C.c_uint32),
+                ("max_bins", C.c_uint32), ("queue_capacity", C.c_uint32), ("seed", C.c_uint32),
+                ("precision", C.c_int), ("energy_budget", C.c_double), ("flags", C.c_uint32)]
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("tracks_in", C.c_uint64), ("tracks_out", C.c_uint64),
+                ("kernel_ms", C.c_double)]
+
+
+class Material(C.Structure):
+    _fields_ = [("Z", C.c_double), ("A", C.c_double), ("density", C.c_double),
+                ("mean_excitation", C.c_double)]
+
+
+class PhysicsOptions(C.Structure):
+    _fields_ = [("tracking_cut", C.c_double), ("production_cut", C.c_double),
+                ("compton", C.c_int32), ("photoelectric", C.c_int32), ("pair", C.c_int32),
+                ("ionisation", C.c_int32), ("brems", C.c_int32), ("annihilation", C.c_int32),
+                ("charged_local", C.c_int32), ("continuous_loss", C.c_int32),
+                ("step_alpha", C.c_double), ("step_rfinal", C.c_double),
+                ("max_steps", C.c_uint32)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_vol", C.c_int32), ("bounds", C.POINTER(C.c_double)),
+                ("material", C.POINTER(C.c_int32)), ("tally_bin", C.POINTER(C.c_int32)),
+                ("n_bins", C.c_int32), ("half_x", C.c_double), ("half_y", C.c_double),
+                ("half_z", C.c_double), ("bz", C.c_double), ("field_tol", C.c_double)]
+
+
+class EventBatch(C.Structure):
+    _fields_ = [("n_events", C.c_uint32), ("event_ids", C.POINTER(C.c_uint32)),
+                ("offsets", C.POINTER(C.c_int64)), ("species", C.c_void_p),
+                ("energy", C.c_void_p), ("pos", C.c_void_p), ("dir", C.c_void_p)]
+
+
+class Progress(C.Structure):
+    _fields_ = [("alive", C.c_uint64), ("queued_primaries", C.c_uint64),
+                ("queued_events", C.c_uint64), ("iterations", C.c_uint64),
+                ("track_steps", C.c_uint64), ("deferred", C.c_uint64),
+                ("peak_alive", C.c_uint64)]
+
+
+class StepRecord(C.Structure):
+    _fields_ = [("dep", C.c_double), ("esc", C.c_double), ("killed", C.c_double),
+                ("step_len", C.c_double), ("limiter", C.c_int32), ("process", C.c_int32),
+                ("n_pair", C.c_int32), ("n_annih", C.c_int32), ("n_out", C.c_int32),
+                ("escaped", C.c_int32)]
+
+
+SOA_FIELDS = [("x", "f8"), ("y", "f8"), ("z", "f8"), ("u", "f8"), ("v", "f8"), ("w", "f8"),
+              ("T", "f8"), ("nlam", "f8"), ("k0", "u4"), ("k1", "u4"), ("k2", "u4"),
+              ("event", "u4"), ("nstep", "u4"), ("species", "i4"), ("vol", "i4")]
+
+
+class TrackSoA(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n, _ in SOA_FIELDS]
+
+
+RECORD_DTYPE = np.dtype([("dep", "f8"), ("esc", "f8"), ("killed", "f8"), ("step_len", "f8"),
+                         ("limiter", "i4"), ("process", "i4"), ("n_pair", "i4"),
+                         ("n_annih", "i4"), ("n_out", "i4"), ("escaped", "i4")])
+assert RECORD_DTYPE.itemsize == C.sizeof(StepRecord)
+
+_P = C.POINTER
+_sigs = {
+    "ems_workspace_bytes": (C.c_size_t, [_P(Config)]),
+    "ems_create": (C.c_int, [_P(Config), C.c_void_p, C.c_size_t, _P(C.c_void_p)]),
+    "ems_destroy": (None, [C.c_void_p]),
+    "ems_last_error": (C.c_char_p, []),
+    "init_physics_tables": (C.c_int, [C.c_void_p, _P(Material), C.c_int32, _P(PhysicsOptions),
+                                      C.c_void_p]),
+    "init_geometry": (C.c_int, [C.c_void_p, _P(Geometry), C.c_void_p]),
+    "transport_events": (C.c_int, [C.c_void_p, _P(EventBatch), C.c_int32, C.c_void_p,
+                                   _P(Progress)]),
+    "tally_read": (C.c_int, [C.c_void_p, C.c_uint32, _P(C.c_uint32), _P(C.c_double),
+                             _P(C.c_double), _P(C.c_int32), C.c_void_p]),
+    "ems_run_counters": (C.c_int, [C.c_void_p, _P(C.c_uint64), _P(C.c_uint64), C.c_void_p]),
+    "ems_step_stats": (C.c_int, [C.c_void_p, _P(KernelStats), C.c_int32]),
+    "ems_step_once": (C.c_int, [C.c_void_p, _P(TrackSoA), C.c_uint32, C.c_void_p, _P(TrackSoA),
+                                _P(C.c_uint32), C.c_void_p]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = list(_sigs)
+
+
+def _check(st: int, where: str, ok=(EMS_OK,)):
+    if st not in ok:
+        raise EmsError(st, where)
+    return st
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _np_ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+# --------------------------------------------------------------------------- raw entry points
+def workspace_bytes(cfg: Config) -> int:
+    return int(_lib.ems_workspace_bytes(C.byref(cfg)))
+
+
+def create(cfg: Config, workspace_ptr: int, nbytes: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.ems_create(C.byref(cfg), C.c_void_p(workspace_ptr), nbytes, C.byref(h)), "ems_create")
+    return h
+
+
+def init_physics_tables(ctx, materials, options, stream=None):
+    mats = (Material * len(materials))(*[Material(*m) for m in materials])
+    o = PhysicsOptions()
+    for f, _ in PhysicsOptions._fields_:
+        setattr(o, f, getattr(options, f))
+    _check(_lib.init_physics_tables(ctx, mats, len(materials), C.byref(o), _stream(stream)),
+           "init_physics_tables")
+
+
+def init_geometry(ctx, geometry, stream=None):
+    b = np.ascontiguousarray(geometry.bounds, np.float64)
+    m = np.ascontiguousarray(geometry.material, np.int32)
+    t = np.ascontiguousarray(geometry.tally_bin, np.int32)
+    g = Geometry(int(geometry.kind), int(m.shape[0]), _np_ptr(b, C.c_double), _np_ptr(m, C.c_int32),
+                 _np_ptr(t, C.c_int32), int(geometry.n_bins), float(geometry.half_x),
+                 float(geometry.half_y), float(geometry.half_z), float(geometry.bz),
+                 float(geometry.field_tol))
+    _check(_lib.init_geometry(ctx, C.byref(g), _stream(stream)), "init_geometry")
+
+
+def transport_events(ctx, batch: Optional["DeviceEvents"], max_iterations: int = -1,
+                     stream=None) -> Progress:
+    pr = Progress()
+    if batch is None:
+        bp = None
+    else:
+        bp = C.byref(batch.c_struct())
+    _check(_lib.transport_events(ctx, bp, int(max_iterations), _stream(stream), C.byref(pr)),
+           "transport_events")
+    return pr
+
+
+def tally_read(ctx, event_ids, n_bins: int, stream=None):
+    ids = np.ascontiguousarray(event_ids, np.uint32)
+    n = ids.shape[0]
+    dep = np.zeros((n, n_bins), np.float64)
+    ledger = np.zeros((n, 5), np.float64)
+    status = np.zeros(n, np.int32)
+    _check(_lib.tally_read(ctx, n, _np_ptr(ids, C.c_uint32), _np_ptr(dep, C.c_double),
+                           _np_ptr(ledger, C.c_double), _np_ptr(status, C.c_int32),
+                           _stream(stream)), "tally_read", ok=(EMS_OK, EMS_NOT_READY))
+    return dep, ledger, status
+
+
+def run_counters(ctx, stream=None):
+    steps = np.zeros(3, np.uint64)
+    hist = np.zeros((3, NGRID), np.uint64)
+    _check(_lib.ems_run_counters(ctx, _np_ptr(steps, C.c_uint64), _np_ptr(hist, C.c_uint64),
+                                 _stream(stream)), "ems_run_counters")
+    return steps, hist
+
+
+# --------------------------------------------------------------------------- torch-side helpers
+class DeviceEvents:
+    """Primaries of a workloads.Events batch, resident on the GPU."""
+
+    def __init__(self, events, device="cuda"):
+        import torch
+        self.ids = np.ascontiguousarray(events.event_ids, np.uint32)
+        self.offsets = np.ascontiguousarray(events.offsets, np.int64)
+        self.species = torch.as_tensor(np.ascontiguousarray(events.species, np.int32), device=device)
+        self.energy = torch.as_tensor(np.ascontiguousarray(events.energy, np.float64), device=device)
+        self.pos = torch.as_tensor(np.ascontiguousarray(events.pos, np.float64), device=device)
+        self.dir = torch.as_tensor(np.ascontiguousarray(events.dir, np.float64), device=device)
+
+    @property
+    def n_events(self):
+        return int(self.ids.shape[0])
+
+    def c_struct(self) -> EventBatch:
+        self._keep = (self.ids, self.offsets)
+        return EventBatch(self.n_events, _np_ptr(self.ids, C.c_uint32), _np_ptr(self.offsets, C.c_int64),
+                          self.species.data_ptr(), self.energy.data_ptr(), self.pos.data_ptr(),
+                          self.dir.data_ptr())
+
+
+class Context:
+    """A transport context over a torch-allocated workspace."""
+
+    def __init__(self, pool_capacity=1 << 20, max_events=1024, max_bins=128,
+                 queue_capacity=1 << 20, seed=1, precision=EMS_FP64, energy_budget=0.0,
+                 time_steps=False, device="cuda"):
+        import torch
+        self.cfg = Config(pool_capacity, max_events, max_bins, queue_capacity, seed, precision,
+                          energy_budget, 1 if time_steps else 0)
+        nbytes = workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise EmsError(-1, "ems_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.h = create(self.cfg, aligned, nbytes)
+        self.n_bins = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ems_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def setup(self, materials, options, geometry, stream=None):
+        init_physics_tables(self.h, materials, options, stream)
+        init_geometry(self.h, geometry, stream)
+        self.n_bins = int(geometry.n_bins)
+
+    def transport(self, batch=None, max_iterations=-1, stream=None) -> Progress:
+        return transport_events(self.h, batch, max_iterations, stream)
+
+    def read(self, event_ids, stream=None):
+        return tally_read(self.h, event_ids, self.n_bins, stream)
+
+    def counters(self, stream=None):
+        return run_counters(self.h, stream)
+
+    def step_stats(self, reset=False) -> KernelStats:
+        st = KernelStats()
+        _check(_lib.ems_step_stats(self.h, C.byref(st), 1 if reset else 0), "ems_step_stats")
+        return st
+
+    def step_once(self, states: dict, stream=None):
+        """Step the given states (dict of numpy arrays: species, energy, vol, pos, dir, nlam,
+        key, nstep, event) once; returns (records, outputs dict of numpy arrays)."""
+        import torch
+        n = len(states["species"])
+        cols = {
+            "x": states["pos"][:, 0], "y": states["pos"][:, 1], "z": states["pos"][:, 2],
+            "u": states["dir"][:, 0], "v": states["dir"][:, 1], "w": states["dir"][:, 2],
+            "T": states["energy"], "nlam": states["nlam"], "k0": states["key"][:, 0],
+            "k1": states["key"][:, 1], "k2": states["key"][:, 2], "event": states["event"],
+            "nstep": states["nstep"], "species": states["species"], "vol": states["vol"],
+        }
+        dev_in = {}
+        for k, dt in SOA_FIELDS:
+            a = np.ascontiguousarray(cols[k], dt)
+            dev_in[k] = torch.as_tensor(a.view(np.int32) if dt == "u4" else a, device="cuda")
+        dev_out = {k: torch.empty(3 * n, dtype=getattr(torch, {"f8": "float64", "u4": "int32",
+                                                             "i4": "int32"}[dt]), device="cuda")
+                   for k, dt in SOA_FIELDS}
+        rec = torch.empty(n * RECORD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        sin = TrackSoA(*[dev_in[k].data_ptr() for k, _ in SOA_FIELDS])
+        sout = TrackSoA(*[dev_out[k].data_ptr() for k, _ in SOA_FIELDS])
+        n_out = C.c_uint32()
+        _check(_lib.ems_step_once(self.h, C.byref(sin), n, C.c_void_p(rec.data_ptr()), C.byref(sout),
+                                  C.byref(n_out), _stream(stream)), "ems_step_once")
+        records = np.frombuffer(rec.cpu().numpy().tobytes(), dtype=RECORD_DTYPE)
+        m = n_out.value
+        out = {}
+        for k, dt in SOA_FIELDS:
+            a = dev_out[k][:m].cpu().numpy()
+            out[k] = a.view(np.uint32) if dt == "u4" else a
+        return records, out

@@ -1,0 +1,76 @@
+// ems_device.h -- data layout shared by the host side of the library and its HIP kernels.
+//
+// Track state lives in HBM as structure-of-arrays, one slot per track, so that
+// consecutive lanes of a wavefront read and write consecutive addresses (paper
+// Sec. 2.1: parameter data separate from per-track state; one track per thread).
+// The pool is double-buffered: a step iteration reads tracks [0, n) of one
+// buffer and writes survivors and secondaries, compacted, into the other.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ems {
+
+constexpr int kGrid = 200;            // nodes of the log energy grid, 1 keV .. 100 GeV
+constexpr int kQ = 4;                 // quantities per (material, species, node)
+constexpr int kMaxMat = 8;
+constexpr int kLedger = 4;            // escaped (fixed point), killed (fixed point), pairs, annihilations
+constexpr uint32_t kVolOut = 0x3FFFFFFFu;  // meta volume of a primary that starts outside
+constexpr uint32_t kRestStep = 0xFFFFFFFFu;
+constexpr int kMaxTrial = 1000;
+constexpr int kBlock = 256;
+
+// Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.
+struct Pool {
+  double *x, *y, *z, *u, *v, *w, *T, *nlam;
+  uint32_t *k0, *k1, *k2, *evt, *nstep, *meta;
+};
+
+struct MatParams {
+  double Tc, kc;      // production thresholds (delta rays, brems photons)
+  double Rtrk[3];     // range table at the tracking cut, per species
+  float Rtrk_f[3];
+  float Tc_f, kc_f;
+  int vacuum;
+};
+
+// Immutable parameters of a run, passed by value to every step launch.
+struct Params {
+  const double* tab_d;  // [mat][species][node][kQ]
+  const float* tab_f;
+  double lnE0, inv_dlnE, dlnE;
+  float lnE0_f, inv_dlnE_f, dlnE_f;
+  MatParams mat[kMaxMat];
+  int n_mats;
+  double tcut, alpha, rfinal;
+  float tcut_f, alpha_f, rfinal_f;
+  uint32_t max_steps;
+  int charged_local, cont_loss;
+  int gkind, nvol, nbins;
+  uint32_t max_events;
+  const double* bounds;
+  const int* vmat;
+  const int* vbin;
+  double hx, hy, hz, bz, ftol;
+  uint32_t seed;
+  // tallies (per event slot) and run counters
+  unsigned long long* tally;     // [slot][nbins], fixed point
+  unsigned long long* ledger;    // [slot][kLedger]
+  int* alive;                    // [slot] tracks alive or queued
+  const double* scale;           // [slot] fixed-point scale 2^s
+  uint32_t* done;                // [slot] list of finished slots (append)
+  uint32_t* counters;            // [0] pool out count, [1] done count
+  unsigned long long* steps;     // [3] track-steps by species
+  unsigned long long* esc_hist;  // [3][kGrid]
+};
+
+// Pending primaries (ring of queue_capacity entries).
+struct Queue {
+  int32_t* species;
+  double *T, *x, *y, *z, *u, *v, *w;
+  uint32_t *slot, *index, *event_id;
+  uint32_t capacity;
+};
+
+}  // namespace ems

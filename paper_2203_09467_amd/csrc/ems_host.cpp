@@ -1,0 +1,612 @@
+// ems_host.cpp -- C ABI of the step loop: context, workspace carving, geometry,
+// event slots and queue, the host iteration loop, tally readout.
+//
+// The host loop per iteration (paper Sec. 3.2: a step is several kernels with
+// synchronisation points; events are batched to keep enough tracks in flight):
+//   1. admit whole queued events while pool room and the energy budget allow
+//      (one kernel appending primaries to the pool);
+//   2. one fused step kernel over the pool, writing the compacted next pool;
+//   3. read back the pool size and the list of events that just finished.
+// The step count of a track, not the iteration, keys its random numbers, so
+// admission order, deferral and pool size change no result.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "emshower.h"
+#include "ems_device.h"
+#include "ems_host.h"
+
+using namespace ems;
+
+namespace {
+
+thread_local std::string g_err;
+
+ems_status fail(ems_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(EMS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kMaxVol = 4096;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carving of the workspace; with base == nullptr it only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + n * sizeof(T));
+    return p;
+  }
+};
+
+struct EventInfo {
+  uint32_t slot;
+  uint32_t n_prim;
+  double e_in;
+};
+
+}  // namespace
+
+struct ems_ctx {
+  ems_config cfg{};
+  Params P{};
+  Pool pool[2]{};
+  Queue q{};
+  int cur = 0;
+  uint32_t n_active = 0;
+  bool tables = false, geometry = false;
+  ems_physics_options opts{};
+  // device regions
+  double* tab_d = nullptr;
+  float* tab_f = nullptr;
+  double* geo_bounds = nullptr;
+  int* geo_mat = nullptr;
+  int* geo_bin = nullptr;
+  double* e_in = nullptr;
+  double* scale = nullptr;
+  int64_t* stage_off = nullptr;
+  uint32_t* stage_slot = nullptr;
+  uint32_t* stage_id = nullptr;
+  double* stage_out = nullptr;
+  uint32_t* counters = nullptr;
+  // pinned host mirror of the counters and done list
+  uint32_t* h_counters = nullptr;
+  uint32_t* h_done = nullptr;
+  // event slots
+  std::vector<uint32_t> free_slots;
+  std::vector<int> slot_state;  // 0 free, 1 queued or in flight, 2 finished
+  std::vector<uint32_t> slot_id;
+  std::vector<double> slot_e;
+  std::unordered_map<uint32_t, uint32_t> id_to_slot;
+  std::deque<EventInfo> pending;
+  uint32_t q_head = 0, q_count = 0;
+  uint64_t pending_prims = 0;
+  double e_flight = 0.0;
+  // step-kernel statistics
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  ems_kernel_stats stats{};
+};
+
+namespace {
+
+void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
+  const size_t N = cfg.pool_capacity, E = cfg.max_events, B = cfg.max_bins, Qc = cfg.queue_capacity;
+  Pool pools[2];
+  for (int b = 0; b < 2; ++b) {
+    Pool& p = pools[b];
+    p.x = c.take<double>(N);
+    p.y = c.take<double>(N);
+    p.z = c.take<double>(N);
+    p.u = c.take<double>(N);
+    p.v = c.take<double>(N);
+    p.w = c.take<double>(N);
+    p.T = c.take<double>(N);
+    p.nlam = c.take<double>(N);
+    p.k0 = c.take<uint32_t>(N);
+    p.k1 = c.take<uint32_t>(N);
+    p.k2 = c.take<uint32_t>(N);
+    p.evt = c.take<uint32_t>(N);
+    p.nstep = c.take<uint32_t>(N);
+    p.meta = c.take<uint32_t>(N);
+  }
+  double* tab_d = c.take<double>((size_t)kMaxMat * 3 * kGrid * kQ);
+  float* tab_f = c.take<float>((size_t)kMaxMat * 3 * kGrid * kQ);
+  double* gb = c.take<double>(kMaxVol + 1);
+  int* gm = c.take<int>(kMaxVol);
+  int* gbin = c.take<int>(kMaxVol);
+  unsigned long long* tally = c.take<unsigned long long>(E * B);
+  unsigned long long* ledger = c.take<unsigned long long>(E * kLedger);
+  int* alive = c.take<int>(E);
+  double* scale = c.take<double>(E);
+  double* e_in = c.take<double>(E);
+  uint32_t* done = c.take<uint32_t>(E);
+  uint32_t* counters = c.take<uint32_t>(16);
+  unsigned long long* steps = c.take<unsigned long long>(4);
+  unsigned long long* esc = c.take<unsigned long long>(3 * kGrid);
+  Queue q;
+  q.species = c.take<int32_t>(Qc);
+  q.T = c.take<double>(Qc);
+  q.x = c.take<double>(Qc);
+  q.y = c.take<double>(Qc);
+  q.z = c.take<double>(Qc);
+  q.u = c.take<double>(Qc);
+  q.v = c.take<double>(Qc);
+  q.w = c.take<double>(Qc);
+  q.slot = c.take<uint32_t>(Qc);
+  q.index = c.take<uint32_t>(Qc);
+  q.event_id = c.take<uint32_t>(Qc);
+  q.capacity = (uint32_t)Qc;
+  int64_t* so = c.take<int64_t>(E + 1);
+  uint32_t* ss = c.take<uint32_t>(E);
+  uint32_t* si = c.take<uint32_t>(E);
+  double* sout = c.take<double>(E * (B + 5));
+  if (!x) return;
+  x->pool[0] = pools[0];
+  x->pool[1] = pools[1];
+  x->tab_d = tab_d;
+  x->tab_f = tab_f;
+  x->geo_bounds = gb;
+  x->geo_mat = gm;
+  x->geo_bin = gbin;
+  x->P.tab_d = tab_d;
+  x->P.tab_f = tab_f;
+  x->P.bounds = gb;
+  x->P.vmat = gm;
+  x->P.vbin = gbin;
+  x->P.tally = tally;
+  x->P.ledger = ledger;
+  x->P.alive = alive;
+  x->P.scale = scale;
+  x->P.done = done;
+  x->P.counters = counters;
+  x->P.steps = steps;
+  x->P.esc_hist = esc;
+  x->scale = scale;
+  x->e_in = e_in;
+  x->counters = counters;
+  x->q = q;
+  x->stage_off = so;
+  x->stage_slot = ss;
+  x->stage_id = si;
+  x->stage_out = sout;
+}
+
+bool config_ok(const ems_config* c) {
+  return c && c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && c->max_events >= 1 &&
+         c->max_bins >= 1 && c->queue_capacity >= 1 &&
+         (c->precision == EMS_FP64 || c->precision == EMS_MIXED);
+}
+
+void reset_events(ems_ctx* x) {
+  const uint32_t E = x->cfg.max_events;
+  x->free_slots.resize(E);
+  for (uint32_t i = 0; i < E; ++i) x->free_slots[i] = E - 1 - i;
+  x->slot_state.assign(E, 0);
+  x->slot_id.assign(E, 0);
+  x->slot_e.assign(E, 0.0);
+  x->id_to_slot.clear();
+  x->pending.clear();
+  x->q_head = 0;
+  x->q_count = 0;
+  x->pending_prims = 0;
+  x->e_flight = 0.0;
+  x->n_active = 0;
+  x->cur = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ems_last_error(void) { return g_err.c_str(); }
+
+size_t ems_workspace_bytes(const ems_config* cfg) {
+  if (!config_ok(cfg)) return 0;
+  Carver c{nullptr};
+  carve(c, *cfg, nullptr);
+  return c.off;
+}
+
+ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, ems_ctx** out) {
+  if (!out) return fail(EMS_E_ARG, "ems_create: out is null");
+  *out = nullptr;
+  if (!config_ok(cfg)) return fail(EMS_E_ARG, "ems_create: invalid configuration");
+  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+    return fail(EMS_E_ARG, "ems_create: workspace must be non-null and 256-byte aligned");
+  const size_t need = ems_workspace_bytes(cfg);
+  if (bytes < need)
+    return fail(EMS_E_CAPACITY, "ems_create: workspace of " + std::to_string(bytes) +
+                                    " bytes, need " + std::to_string(need));
+  ems_ctx* x = new (std::nothrow) ems_ctx();
+  if (!x) return fail(EMS_E_INTERNAL, "ems_create: out of host memory");
+  x->cfg = *cfg;
+  Carver c{static_cast<char*>(d_workspace)};
+  carve(c, *cfg, x);
+  x->P.seed = cfg->seed;
+  x->P.max_events = cfg->max_events;
+  hipError_t e = hipHostMalloc((void**)&x->h_counters, 16 * sizeof(uint32_t), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
+                      hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (x->h_counters) (void)hipHostFree(x->h_counters);
+    delete x;
+    return fail(EMS_E_HIP, std::string("ems_create: pinned host buffer: ") + hipGetErrorString(e));
+  }
+  if (cfg->flags & EMS_FLAG_TIME_STEPS) {
+    if (hipEventCreate(&x->ev0) != hipSuccess || hipEventCreate(&x->ev1) != hipSuccess) {
+      ems_destroy(x);
+      return fail(EMS_E_HIP, "ems_create: hipEventCreate failed");
+    }
+  }
+  reset_events(x);
+  *out = x;
+  return EMS_OK;
+}
+
+void ems_destroy(ems_ctx* x) {
+  if (!x) return;
+  if (x->h_counters) (void)hipHostFree(x->h_counters);
+  if (x->h_done) (void)hipHostFree(x->h_done);
+  if (x->ev0) (void)hipEventDestroy(x->ev0);
+  if (x->ev1) (void)hipEventDestroy(x->ev1);
+  delete x;
+}
+
+ems_status init_physics_tables(ems_ctx* x, const ems_material* mats, int32_t n_mats,
+                               const ems_physics_options* o, void* stream) {
+  if (!x || !o || (n_mats > 0 && !mats)) return fail(EMS_E_ARG, "init_physics_tables: null argument");
+  if (n_mats < 1 || n_mats > kMaxMat) return fail(EMS_E_ARG, "init_physics_tables: 1..8 materials");
+  if (!(o->tracking_cut > 0.0) || !(o->step_alpha > 0.0 && o->step_alpha <= 1.0) ||
+      !(o->step_rfinal > 0.0) || o->max_steps < 1)
+    return fail(EMS_E_ARG, "init_physics_tables: invalid options");
+  std::vector<double> tab;
+  MatParams mp[kMaxMat];
+  std::memset(mp, 0, sizeof(mp));
+  if (ems::build_physics_tables(mats, n_mats, *o, tab, mp) != 0)
+    return fail(EMS_E_ARG, "init_physics_tables: invalid material");
+  std::vector<float> tabf(tab.size());
+  for (size_t i = 0; i < tab.size(); ++i) tabf[i] = (float)tab[i];
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(x->tab_d, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(x->tab_f, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  Params& P = x->P;
+  P.lnE0 = std::log(1.0e-3);
+  P.dlnE = std::log(1.0e8) / (kGrid - 1);
+  P.inv_dlnE = 1.0 / P.dlnE;
+  P.lnE0_f = (float)P.lnE0;
+  P.dlnE_f = (float)P.dlnE;
+  P.inv_dlnE_f = (float)P.inv_dlnE;
+  for (int m = 0; m < kMaxMat; ++m) P.mat[m] = mp[m];
+  P.n_mats = n_mats;
+  P.tcut = o->tracking_cut;
+  P.alpha = o->step_alpha;
+  P.rfinal = o->step_rfinal;
+  P.tcut_f = (float)P.tcut;
+  P.alpha_f = (float)P.alpha;
+  P.rfinal_f = (float)P.rfinal;
+  P.max_steps = o->max_steps;
+  P.charged_local = o->charged_local != 0;
+  P.cont_loss = o->continuous_loss != 0;
+  x->opts = *o;
+  x->tables = true;
+  x->geometry = false;
+  return EMS_OK;
+}
+
+ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
+  if (!x || !g || !g->bounds || !g->material || !g->tally_bin)
+    return fail(EMS_E_ARG, "init_geometry: null argument");
+  if (!x->tables) return fail(EMS_E_STATE, "init_geometry: call init_physics_tables first");
+  if (g->kind != EMS_GEOM_SLABS && g->kind != EMS_GEOM_CYLINDERS)
+    return fail(EMS_E_ARG, "init_geometry: unknown kind");
+  if (g->n_vol < 1 || (uint32_t)g->n_vol > kMaxVol) return fail(EMS_E_ARG, "init_geometry: 1..4096 volumes");
+  if (g->n_bins < 1 || (uint32_t)g->n_bins > x->cfg.max_bins)
+    return fail(EMS_E_ARG, "init_geometry: n_bins exceeds the configured max_bins");
+  for (int i = 0; i < g->n_vol; ++i) {
+    if (!(g->bounds[i + 1] > g->bounds[i])) return fail(EMS_E_ARG, "init_geometry: bounds must increase");
+    if (g->material[i] < -1 || g->material[i] >= x->P.n_mats)
+      return fail(EMS_E_ARG, "init_geometry: unknown material index");
+    if (g->tally_bin[i] < 0 || g->tally_bin[i] >= g->n_bins)
+      return fail(EMS_E_ARG, "init_geometry: tally bin out of range");
+  }
+  if (g->kind == EMS_GEOM_SLABS && !(g->half_x > 0 && g->half_y > 0))
+    return fail(EMS_E_ARG, "init_geometry: slab half widths must be positive");
+  if (g->kind == EMS_GEOM_CYLINDERS && !(g->half_z > 0 && g->bounds[0] == 0.0))
+    return fail(EMS_E_ARG, "init_geometry: shells need half_z > 0 and a first radius of 0");
+  if (g->bz != 0.0) return fail(EMS_E_ARG, "init_geometry: magnetic field not supported yet");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(x->geo_bounds, g->bounds, sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(x->geo_mat, g->material, sizeof(int) * g->n_vol, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(x->geo_bin, g->tally_bin, sizeof(int) * g->n_vol, hipMemcpyHostToDevice, s));
+  Params& P = x->P;
+  P.gkind = g->kind;
+  P.nvol = g->n_vol;
+  P.nbins = g->n_bins;
+  P.hx = g->half_x;
+  P.hy = g->half_y;
+  P.hz = g->half_z;
+  P.bz = g->bz;
+  P.ftol = g->field_tol;
+  HIP_OK(launch_zero_u32(x->counters, 16, s));
+  HIP_OK(launch_zero_u64(P.steps, 4, s));
+  HIP_OK(launch_zero_u64(P.esc_hist, 3 * kGrid, s));
+  HIP_OK(hipStreamSynchronize(s));
+  reset_events(x);
+  x->geometry = true;
+  return EMS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Submit a batch: slots, ring copy, slot initialisation.  Nothing changes on error.
+ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
+  const uint32_t ne = b->n_events;
+  if (ne == 0) return EMS_OK;
+  if (!b->event_ids || !b->offsets) return fail(EMS_E_ARG, "transport_events: null ids/offsets");
+  if (b->offsets[0] != 0) return fail(EMS_E_ARG, "transport_events: offsets[0] must be 0");
+  for (uint32_t e = 0; e < ne; ++e)
+    if (b->offsets[e + 1] < b->offsets[e] + 1)
+      return fail(EMS_E_ARG, "transport_events: every event needs at least one primary");
+  const uint64_t n = (uint64_t)b->offsets[ne];
+  if (!b->species || !b->energy || !b->pos || !b->dir)
+    return fail(EMS_E_ARG, "transport_events: null primary arrays");
+  if (ne > x->free_slots.size())
+    return fail(EMS_E_CAPACITY, "transport_events: not enough free event slots");
+  if (n + x->q_count > x->cfg.queue_capacity)
+    return fail(EMS_E_CAPACITY, "transport_events: primaries exceed the queue capacity");
+  for (uint32_t e = 0; e < ne; ++e) {
+    if (x->id_to_slot.count(b->event_ids[e])) return fail(EMS_E_ARG, "transport_events: duplicate event id");
+    if ((uint64_t)(b->offsets[e + 1] - b->offsets[e]) > x->cfg.pool_capacity / 4)
+      return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
+  }
+  {
+    std::unordered_map<uint32_t, int> seen;
+    for (uint32_t e = 0; e < ne; ++e)
+      if (seen[b->event_ids[e]]++) return fail(EMS_E_ARG, "transport_events: duplicate event id in batch");
+  }
+  std::vector<uint32_t> slots(ne);
+  for (uint32_t e = 0; e < ne; ++e) slots[e] = x->free_slots[x->free_slots.size() - 1 - e];
+  HIP_OK(hipMemcpyAsync(x->stage_off, b->offsets, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(x->stage_slot, slots.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
+  const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
+  HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
+                        b->energy, b->pos, b->dir, (uint32_t)n, s));
+  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, ne, x->e_in, x->scale, s));
+  // primary energy per slot, for the admission energy budget
+  std::vector<double> ein(x->cfg.max_events);
+  HIP_OK(hipMemcpyAsync(ein.data(), x->e_in, ein.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<double> ev_e(ne);
+  for (uint32_t e = 0; e < ne; ++e) ev_e[e] = ein[slots[e]];
+  for (uint32_t e = 0; e < ne; ++e) {
+    const uint32_t sl = slots[e];
+    x->free_slots.pop_back();
+    x->slot_state[sl] = 1;
+    x->slot_id[sl] = b->event_ids[e];
+    x->slot_e[sl] = ev_e[e];
+    x->id_to_slot[b->event_ids[e]] = sl;
+    x->pending.push_back({sl, (uint32_t)(b->offsets[e + 1] - b->offsets[e]), ev_e[e]});
+  }
+  x->q_count += (uint32_t)n;
+  x->pending_prims += n;
+  return EMS_OK;
+}
+
+// Admit queued events (whole) into the current pool.
+ems_status admit(ems_ctx* x, hipStream_t s) {
+  uint32_t m = 0;
+  const uint32_t room = x->cfg.pool_capacity / 4;  // keep room for the showers to grow
+  const double budget = x->cfg.energy_budget;
+  while (!x->pending.empty()) {
+    const EventInfo& ev = x->pending.front();
+    const bool first = x->n_active + m == 0;
+    if (!first && x->n_active + m + ev.n_prim > room) break;
+    if (budget > 0.0 && x->e_flight > 0.0 && x->e_flight + ev.e_in > budget) break;
+    m += ev.n_prim;
+    x->e_flight += ev.e_in;
+    x->pending.pop_front();
+  }
+  if (m == 0) return EMS_OK;
+  HIP_OK(launch_admit(x->P, x->q, x->pool[x->cur], x->q_head, m, x->n_active, s));
+  x->q_head = (x->q_head + m) % x->q.capacity;
+  x->q_count -= m;
+  x->pending_prims -= m;
+  x->n_active += m;
+  return EMS_OK;
+}
+
+// One step iteration and its readback.
+ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* stepped,
+                   uint64_t* deferred) {
+  const uint32_t n = x->n_active;
+  const uint32_t cap = x->cfg.pool_capacity;
+  const uint32_t k = std::min<uint64_t>(n, (uint64_t)(cap - n) / 2);
+  if (k == 0) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
+  HIP_OK(launch_zero_u32(x->counters, 2, s));
+  if (x->ev0) HIP_OK(hipEventRecord(x->ev0, s));
+  HIP_OK(launch_step(x->P, x->pool[x->cur], x->pool[1 - x->cur], n, k,
+                     x->cfg.precision == EMS_MIXED, rec, s));
+  if (x->ev1) HIP_OK(hipEventRecord(x->ev1, s));
+  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const uint32_t n_out = x->h_counters[0], n_done = x->h_counters[1];
+  x->stats.launches += 1;
+  x->stats.tracks_in += n;
+  x->stats.tracks_out += n_out;
+  if (x->ev0) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, x->ev0, x->ev1));
+    x->stats.kernel_ms += ms;
+  }
+  if (n_done) {
+    HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, n_done * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (uint32_t j = 0; j < n_done; ++j) {
+      const uint32_t sl = x->h_done[j];
+      if (sl < x->slot_state.size() && x->slot_state[sl] == 1) {
+        x->slot_state[sl] = 2;
+        x->e_flight -= x->slot_e[sl];
+      }
+    }
+    if (x->e_flight < 0.0) x->e_flight = 0.0;
+  }
+  x->n_active = n_out;
+  x->cur = 1 - x->cur;
+  *stepped += k;
+  *deferred += n - k;
+  return EMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_iterations,
+                            void* stream, ems_progress* progress) {
+  if (!x) return fail(EMS_E_ARG, "transport_events: null context");
+  if (!x->tables || !x->geometry) return fail(EMS_E_STATE, "transport_events: initialise tables and geometry first");
+  hipStream_t s = (hipStream_t)stream;
+  if (b) {
+    const ems_status st = submit(x, b, s);
+    if (st != EMS_OK) return st;
+  }
+  uint64_t it = 0, stepped = 0, deferred = 0, peak = x->n_active;
+  while (max_iterations < 0 || it < (uint64_t)max_iterations) {
+    ems_status st = admit(x, s);
+    if (st != EMS_OK) return st;
+    if (x->n_active == 0) {
+      if (x->pending.empty()) break;
+      return fail(EMS_E_INTERNAL, "transport_events: queued events could not be admitted");
+    }
+    peak = std::max<uint64_t>(peak, x->n_active);
+    st = iterate(x, s, nullptr, &stepped, &deferred);
+    if (st != EMS_OK) return st;
+    ++it;
+  }
+  if (progress) {
+    progress->alive = x->n_active;
+    progress->queued_primaries = x->pending_prims;
+    progress->queued_events = x->pending.size();
+    progress->iterations = it;
+    progress->track_steps = stepped;
+    progress->deferred = deferred;
+    progress->peak_alive = peak;
+  }
+  return EMS_OK;
+}
+
+ems_status tally_read(ems_ctx* x, uint32_t n, const uint32_t* ids, double* dep, double* ledger,
+                      int32_t* status, void* stream) {
+  if (!x || (n && (!ids || !dep || !ledger || !status))) return fail(EMS_E_ARG, "tally_read: null argument");
+  if (!x->geometry) return fail(EMS_E_STATE, "tally_read: no geometry");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint32_t> slots;
+  std::vector<uint32_t> rows;
+  bool all = true;
+  for (uint32_t j = 0; j < n; ++j) {
+    auto it = x->id_to_slot.find(ids[j]);
+    if (it == x->id_to_slot.end()) {
+      status[j] = EMS_E_ARG;
+      all = false;
+    } else if (x->slot_state[it->second] != 2) {
+      status[j] = EMS_NOT_READY;
+      all = false;
+    } else {
+      status[j] = EMS_OK;
+      slots.push_back(it->second);
+      rows.push_back(j);
+    }
+  }
+  const uint32_t nb = (uint32_t)x->P.nbins;
+  const uint32_t w = nb + 5;
+  const uint32_t chunk = x->cfg.max_events;
+  std::vector<double> buf;
+  for (size_t a = 0; a < slots.size(); a += chunk) {
+    const uint32_t m = (uint32_t)std::min<size_t>(chunk, slots.size() - a);
+    HIP_OK(hipMemcpyAsync(x->stage_slot, slots.data() + a, m * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_OK(launch_gather_tallies(x->P, x->stage_slot, m, x->e_in, x->stage_out, s));
+    buf.resize((size_t)m * w);
+    HIP_OK(hipMemcpyAsync(buf.data(), x->stage_out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (uint32_t r = 0; r < m; ++r) {
+      const uint32_t j = rows[a + r];
+      std::memcpy(dep + (size_t)j * nb, buf.data() + (size_t)r * w, nb * sizeof(double));
+      std::memcpy(ledger + (size_t)j * 5, buf.data() + (size_t)r * w + nb, 5 * sizeof(double));
+    }
+  }
+  for (uint32_t sl : slots) {  // release
+    x->id_to_slot.erase(x->slot_id[sl]);
+    x->slot_state[sl] = 0;
+    x->free_slots.push_back(sl);
+  }
+  return all ? EMS_OK : EMS_NOT_READY;
+}
+
+ems_status ems_run_counters(ems_ctx* x, uint64_t* steps, uint64_t* esc_hist, void* stream) {
+  if (!x || !steps) return fail(EMS_E_ARG, "ems_run_counters: null argument");
+  if (!x->geometry) return fail(EMS_E_STATE, "ems_run_counters: no geometry");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long st[4];
+  HIP_OK(hipMemcpyAsync(st, x->P.steps, sizeof(st), hipMemcpyDeviceToHost, s));
+  if (esc_hist)
+    HIP_OK(hipMemcpyAsync(esc_hist, x->P.esc_hist, 3 * kGrid * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int i = 0; i < 3; ++i) steps[i] = st[i];
+  return EMS_OK;
+}
+
+ems_status ems_step_stats(ems_ctx* x, ems_kernel_stats* out, int32_t reset) {
+  if (!x || !out) return fail(EMS_E_ARG, "ems_step_stats: null argument");
+  *out = x->stats;
+  if (reset) x->stats = ems_kernel_stats{};
+  return EMS_OK;
+}
+
+ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_step_record* rec,
+                         ems_track_soa* out, uint32_t* n_out, void* stream) {
+  if (!x || !in || !rec || !out || !n_out) return fail(EMS_E_ARG, "ems_step_once: null argument");
+  if (!x->tables || !x->geometry) return fail(EMS_E_STATE, "ems_step_once: initialise tables and geometry first");
+  if (n == 0 || (uint64_t)3 * n > x->cfg.pool_capacity)
+    return fail(EMS_E_CAPACITY, "ems_step_once: 3 n must fit the pool");
+  hipStream_t s = (hipStream_t)stream;
+  // every slot of this context is reset: step_once discards any events in flight
+  reset_events(x);
+  HIP_OK(launch_slots_reset(x->P, s));
+  HIP_OK(launch_pool_load(x->pool[0], *in, n, s));
+  x->n_active = n;
+  uint64_t stepped = 0, deferred = 0;
+  ems_status st = iterate(x, s, rec, &stepped, &deferred);
+  if (st != EMS_OK) return st;
+  HIP_OK(launch_pool_dump(x->pool[x->cur], *out, x->n_active, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *n_out = x->n_active;
+  x->n_active = 0;
+  return EMS_OK;
+}
+
+}  // extern "C"
