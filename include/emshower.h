@@ -74,6 +74,7 @@ typedef struct {
   uint64_t launches;
   uint64_t tracks_in;   /* tracks read by the step kernel (stepped + deferred) */
   uint64_t tracks_out;  /* tracks written (survivors + secondaries) */
+  uint64_t queued;      /* tracks passed from transport to the interaction kernel */
   double kernel_ms;     /* summed durations (EMS_FLAG_TIME_STEPS), else 0 */
 } ems_kernel_stats;
 

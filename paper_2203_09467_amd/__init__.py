@@ -53,7 +53,7 @@ class Config(C.Structure):
 
 class KernelStats(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("tracks_in", C.c_uint64), ("tracks_out", C.c_uint64),
-                ("kernel_ms", C.c_double)]
+                ("queued", C.c_uint64), ("kernel_ms", C.c_double)]
 
 
 class Material(C.Structure):

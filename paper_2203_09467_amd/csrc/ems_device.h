@@ -21,10 +21,33 @@ constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
 constexpr int kBlock = 256;
 
-// Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.
+// Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.  Photons and
+// charged tracks live in separate pools so that a wavefront steps one species
+// class.  src (diagnostics only) is the input index of a single-step call.
 struct Pool {
   double *x, *y, *z, *u, *v, *w, *T, *nlam;
-  uint32_t *k0, *k1, *k2, *evt, *nstep, *meta;
+  uint32_t *k0, *k1, *k2, *evt, *nstep, *meta, *src;
+};
+
+// Tracks that ended their step in a discrete interaction (or a positron that
+// stopped), one queue per process so that the interaction kernel runs each
+// process in wavefronts of its own.  Post-step state with the step count not yet
+// incremented (it keys the interaction's random numbers and children).
+enum QueueId {
+  kQCompton = 0, kQPhoto = 1, kQPair = 2, kQMoller = 3, kQBhabha = 4, kQBrems = 5,
+  kQAnnihilation = 6, kQRest = 7, kNumQueues = 8
+};
+
+struct IQueue {
+  double *x, *y, *z, *u, *v, *w, *T;
+  uint32_t *k0, *k1, *k2, *evt, *nstep, *meta, *src;
+  uint32_t capacity;  // per queue; queue q occupies [q * capacity, (q + 1) * capacity)
+};
+
+// Device counters of one iteration.
+enum CounterId {
+  kCOutG = 0, kCOutC = 1, kCDone = 2, kCQueue = 3,  // kCQueue + q: queue sizes
+  kCAdmitG = 11, kCAdmitC = 12, kNumCounters = 16
 };
 
 struct MatParams {
@@ -60,7 +83,7 @@ struct Params {
   int* alive;                    // [slot] tracks alive or queued
   const double* scale;           // [slot] fixed-point scale 2^s
   uint32_t* done;                // [slot] list of finished slots (append)
-  uint32_t* counters;            // [0] pool out count, [1] done count
+  uint32_t* counters;            // CounterId
   unsigned long long* steps;     // [3] track-steps by species
   unsigned long long* esc_hist;  // [3][kGrid]
 };

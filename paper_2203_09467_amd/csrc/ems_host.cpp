@@ -61,7 +61,7 @@ struct Carver {
 
 struct EventInfo {
   uint32_t slot;
-  uint32_t n_prim;
+  uint32_t n_prim, n_gamma;  // primaries, of which photons
   double e_in;
 };
 
@@ -70,10 +70,11 @@ struct EventInfo {
 struct ems_ctx {
   ems_config cfg{};
   Params P{};
-  Pool pool[2]{};
+  Pool pool[2][2]{};  // [class: photon, charged][buffer]
+  IQueue iq{};
   Queue q{};
   int cur = 0;
-  uint32_t n_active = 0;
+  uint32_t nG = 0, nC = 0;  // tracks in the current photon / charged pool
   bool tables = false, geometry = false;
   ems_physics_options opts{};
   // device regions
@@ -111,24 +112,43 @@ namespace {
 
 void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   const size_t N = cfg.pool_capacity, E = cfg.max_events, B = cfg.max_bins, Qc = cfg.queue_capacity;
-  Pool pools[2];
-  for (int b = 0; b < 2; ++b) {
-    Pool& p = pools[b];
-    p.x = c.take<double>(N);
-    p.y = c.take<double>(N);
-    p.z = c.take<double>(N);
-    p.u = c.take<double>(N);
-    p.v = c.take<double>(N);
-    p.w = c.take<double>(N);
-    p.T = c.take<double>(N);
-    p.nlam = c.take<double>(N);
-    p.k0 = c.take<uint32_t>(N);
-    p.k1 = c.take<uint32_t>(N);
-    p.k2 = c.take<uint32_t>(N);
-    p.evt = c.take<uint32_t>(N);
-    p.nstep = c.take<uint32_t>(N);
-    p.meta = c.take<uint32_t>(N);
-  }
+  Pool pools[2][2];
+  for (int cl = 0; cl < 2; ++cl)
+    for (int b = 0; b < 2; ++b) {
+      Pool& p = pools[cl][b];
+      p.x = c.take<double>(N);
+      p.y = c.take<double>(N);
+      p.z = c.take<double>(N);
+      p.u = c.take<double>(N);
+      p.v = c.take<double>(N);
+      p.w = c.take<double>(N);
+      p.T = c.take<double>(N);
+      p.nlam = c.take<double>(N);
+      p.k0 = c.take<uint32_t>(N);
+      p.k1 = c.take<uint32_t>(N);
+      p.k2 = c.take<uint32_t>(N);
+      p.evt = c.take<uint32_t>(N);
+      p.nstep = c.take<uint32_t>(N);
+      p.meta = c.take<uint32_t>(N);
+      p.src = c.take<uint32_t>(N);
+    }
+  IQueue iq;
+  const size_t NQ = (size_t)kNumQueues * N;
+  iq.x = c.take<double>(NQ);
+  iq.y = c.take<double>(NQ);
+  iq.z = c.take<double>(NQ);
+  iq.u = c.take<double>(NQ);
+  iq.v = c.take<double>(NQ);
+  iq.w = c.take<double>(NQ);
+  iq.T = c.take<double>(NQ);
+  iq.k0 = c.take<uint32_t>(NQ);
+  iq.k1 = c.take<uint32_t>(NQ);
+  iq.k2 = c.take<uint32_t>(NQ);
+  iq.evt = c.take<uint32_t>(NQ);
+  iq.nstep = c.take<uint32_t>(NQ);
+  iq.meta = c.take<uint32_t>(NQ);
+  iq.src = c.take<uint32_t>(NQ);
+  iq.capacity = (uint32_t)N;
   double* tab_d = c.take<double>((size_t)kMaxMat * 3 * kGrid * kQ);
   float* tab_f = c.take<float>((size_t)kMaxMat * 3 * kGrid * kQ);
   double* gb = c.take<double>(kMaxVol + 1);
@@ -140,7 +160,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   double* scale = c.take<double>(E);
   double* e_in = c.take<double>(E);
   uint32_t* done = c.take<uint32_t>(E);
-  uint32_t* counters = c.take<uint32_t>(16);
+  uint32_t* counters = c.take<uint32_t>(kNumCounters);
   unsigned long long* steps = c.take<unsigned long long>(4);
   unsigned long long* esc = c.take<unsigned long long>(3 * kGrid);
   Queue q;
@@ -161,8 +181,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   uint32_t* si = c.take<uint32_t>(E);
   double* sout = c.take<double>(E * (B + 5));
   if (!x) return;
-  x->pool[0] = pools[0];
-  x->pool[1] = pools[1];
+  for (int cl = 0; cl < 2; ++cl)
+    for (int b = 0; b < 2; ++b) x->pool[cl][b] = pools[cl][b];
+  x->iq = iq;
   x->tab_d = tab_d;
   x->tab_f = tab_f;
   x->geo_bounds = gb;
@@ -210,7 +231,7 @@ void reset_events(ems_ctx* x) {
   x->q_count = 0;
   x->pending_prims = 0;
   x->e_flight = 0.0;
-  x->n_active = 0;
+  x->nG = x->nC = 0;
   x->cur = 0;
 }
 
@@ -244,7 +265,7 @@ ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, em
   carve(c, *cfg, x);
   x->P.seed = cfg->seed;
   x->P.max_events = cfg->max_events;
-  hipError_t e = hipHostMalloc((void**)&x->h_counters, 16 * sizeof(uint32_t), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&x->h_counters, kNumCounters * sizeof(uint32_t), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
                       hipHostMallocDefault);
@@ -349,7 +370,7 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
   P.hz = g->half_z;
   P.bz = g->bz;
   P.ftol = g->field_tol;
-  HIP_OK(launch_zero_u32(x->counters, 16, s));
+  HIP_OK(launch_zero_u32(x->counters, kNumCounters, s));
   HIP_OK(launch_zero_u64(P.steps, 4, s));
   HIP_OK(launch_zero_u64(P.esc_hist, 3 * kGrid, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -397,12 +418,16 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
                         b->energy, b->pos, b->dir, (uint32_t)n, s));
   HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, ne, x->e_in, x->scale, s));
-  // primary energy per slot, for the admission energy budget
+  // primary energy per slot (admission energy budget) and photons per event (pool sizes)
   std::vector<double> ein(x->cfg.max_events);
+  std::vector<int32_t> sp(n);
   HIP_OK(hipMemcpyAsync(ein.data(), x->e_in, ein.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(sp.data(), b->species, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   std::vector<double> ev_e(ne);
   for (uint32_t e = 0; e < ne; ++e) ev_e[e] = ein[slots[e]];
+  for (uint64_t r = 0; r < n; ++r)
+    if (sp[r] < 0 || sp[r] > 2) return fail(EMS_E_ARG, "transport_events: species must be 0, 1 or 2");
   for (uint32_t e = 0; e < ne; ++e) {
     const uint32_t sl = slots[e];
     x->free_slots.pop_back();
@@ -410,54 +435,75 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
     x->slot_id[sl] = b->event_ids[e];
     x->slot_e[sl] = ev_e[e];
     x->id_to_slot[b->event_ids[e]] = sl;
-    x->pending.push_back({sl, (uint32_t)(b->offsets[e + 1] - b->offsets[e]), ev_e[e]});
+    uint32_t ng = 0;
+    for (int64_t r = b->offsets[e]; r < b->offsets[e + 1]; ++r) ng += sp[r] == EMS_GAMMA;
+    x->pending.push_back({sl, (uint32_t)(b->offsets[e + 1] - b->offsets[e]), ng, ev_e[e]});
   }
   x->q_count += (uint32_t)n;
   x->pending_prims += n;
   return EMS_OK;
 }
 
-// Admit queued events (whole) into the current pool.
-ems_status admit(ems_ctx* x, hipStream_t s) {
-  uint32_t m = 0;
+// Admit queued events (whole) into the current pools.  The admission kernel runs
+// after k_iter_begin has set the admission cursors to the pool sizes.
+ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
+  uint32_t m = 0, mg = 0;
   const uint32_t room = x->cfg.pool_capacity / 4;  // keep room for the showers to grow
   const double budget = x->cfg.energy_budget;
+  const uint32_t n_active = x->nG + x->nC;
   while (!x->pending.empty()) {
     const EventInfo& ev = x->pending.front();
-    const bool first = x->n_active + m == 0;
-    if (!first && x->n_active + m + ev.n_prim > room) break;
+    const bool first = n_active + m == 0;
+    if (!first && n_active + m + ev.n_prim > room) break;
     if (budget > 0.0 && x->e_flight > 0.0 && x->e_flight + ev.e_in > budget) break;
     m += ev.n_prim;
+    mg += ev.n_gamma;
     x->e_flight += ev.e_in;
     x->pending.pop_front();
   }
+  *m_out = m;
   if (m == 0) return EMS_OK;
-  HIP_OK(launch_admit(x->P, x->q, x->pool[x->cur], x->q_head, m, x->n_active, s));
+  HIP_OK(launch_admit(x->P, x->q, x->pool[0][x->cur], x->pool[1][x->cur], x->q_head, m, s));
   x->q_head = (x->q_head + m) % x->q.capacity;
   x->q_count -= m;
   x->pending_prims -= m;
-  x->n_active += m;
+  x->nG += mg;
+  x->nC += m - mg;
   return EMS_OK;
 }
 
-// One step iteration and its readback.
+// One step iteration (admission, transport, interactions) and its readback.
 ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* stepped,
-                   uint64_t* deferred) {
-  const uint32_t n = x->n_active;
+                   uint64_t* deferred, bool admit_first) {
+  HIP_OK(launch_iter_begin(x->counters, x->nG, x->nC, s));
+  if (admit_first) {
+    uint32_t m = 0;
+    const ems_status st = admit(x, s, &m);
+    if (st != EMS_OK) return st;
+  }
+  const uint32_t nG = x->nG, nC = x->nC, n = nG + nC;
+  if (n == 0) return EMS_OK;
   const uint32_t cap = x->cfg.pool_capacity;
+  // every stepped track leaves at most three tracks, so n + 2k <= cap bounds both pools
   const uint32_t k = std::min<uint64_t>(n, (uint64_t)(cap - n) / 2);
   if (k == 0) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
-  HIP_OK(launch_zero_u32(x->counters, 2, s));
+  const uint32_t kG = std::min(nG, k), kC = std::min(nC, k - kG);
   if (x->ev0) HIP_OK(hipEventRecord(x->ev0, s));
-  HIP_OK(launch_step(x->P, x->pool[x->cur], x->pool[1 - x->cur], n, k,
-                     x->cfg.precision == EMS_MIXED, rec, s));
+  HIP_OK(launch_iteration(x->P, x->pool[0][x->cur], x->pool[1][x->cur], nG, kG, nC, kC,
+                          x->pool[0][1 - x->cur], x->pool[1][1 - x->cur], x->iq,
+                          x->cfg.precision == EMS_MIXED, rec, s));
   if (x->ev1) HIP_OK(hipEventRecord(x->ev1, s));
-  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, kNumCounters * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  const uint32_t n_out = x->h_counters[0], n_done = x->h_counters[1];
+  const uint32_t outG = x->h_counters[kCOutG], outC = x->h_counters[kCOutC];
+  const uint32_t n_done = std::min(x->h_counters[kCDone], x->cfg.max_events);
   x->stats.launches += 1;
   x->stats.tracks_in += n;
-  x->stats.tracks_out += n_out;
+  x->stats.tracks_out += (uint64_t)outG + outC;
+  uint64_t queued = 0;
+  for (int q = 0; q < kNumQueues; ++q) queued += x->h_counters[kCQueue + q];
+  x->stats.queued += queued;
   if (x->ev0) {
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, x->ev0, x->ev1));
@@ -475,7 +521,8 @@ ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* st
     }
     if (x->e_flight < 0.0) x->e_flight = 0.0;
   }
-  x->n_active = n_out;
+  x->nG = outG;
+  x->nC = outC;
   x->cur = 1 - x->cur;
   *stepped += k;
   *deferred += n - k;
@@ -495,21 +542,16 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
     const ems_status st = submit(x, b, s);
     if (st != EMS_OK) return st;
   }
-  uint64_t it = 0, stepped = 0, deferred = 0, peak = x->n_active;
+  uint64_t it = 0, stepped = 0, deferred = 0, peak = (uint64_t)x->nG + x->nC;
   while (max_iterations < 0 || it < (uint64_t)max_iterations) {
-    ems_status st = admit(x, s);
+    if (x->nG + x->nC == 0 && x->pending.empty()) break;
+    const ems_status st = iterate(x, s, nullptr, &stepped, &deferred, true);
     if (st != EMS_OK) return st;
-    if (x->n_active == 0) {
-      if (x->pending.empty()) break;
-      return fail(EMS_E_INTERNAL, "transport_events: queued events could not be admitted");
-    }
-    peak = std::max<uint64_t>(peak, x->n_active);
-    st = iterate(x, s, nullptr, &stepped, &deferred);
-    if (st != EMS_OK) return st;
+    peak = std::max<uint64_t>(peak, (uint64_t)x->nG + x->nC);
     ++it;
   }
   if (progress) {
-    progress->alive = x->n_active;
+    progress->alive = (uint64_t)x->nG + x->nC;
     progress->queued_primaries = x->pending_prims;
     progress->queued_events = x->pending.size();
     progress->iterations = it;
@@ -597,15 +639,21 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   // every slot of this context is reset: step_once discards any events in flight
   reset_events(x);
   HIP_OK(launch_slots_reset(x->P, s));
-  HIP_OK(launch_pool_load(x->pool[0], *in, n, s));
-  x->n_active = n;
-  uint64_t stepped = 0, deferred = 0;
-  ems_status st = iterate(x, s, rec, &stepped, &deferred);
-  if (st != EMS_OK) return st;
-  HIP_OK(launch_pool_dump(x->pool[x->cur], *out, x->n_active, s));
+  HIP_OK(launch_iter_begin(x->counters, 0, 0, s));
+  HIP_OK(launch_pool_load(x->P, x->pool[0][0], x->pool[1][0], *in, n, s));
+  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, kNumCounters * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  *n_out = x->n_active;
-  x->n_active = 0;
+  x->nG = x->h_counters[kCAdmitG];
+  x->nC = x->h_counters[kCAdmitC];
+  uint64_t stepped = 0, deferred = 0;
+  ems_status st = iterate(x, s, rec, &stepped, &deferred, false);
+  if (st != EMS_OK) return st;
+  HIP_OK(launch_pool_dump(x->pool[0][x->cur], *out, x->nG, 0, s));
+  HIP_OK(launch_pool_dump(x->pool[1][x->cur], *out, x->nC, x->nG, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *n_out = x->nG + x->nC;
+  x->nG = x->nC = 0;
   return EMS_OK;
 }
 

@@ -330,7 +330,13 @@ __device__ __forceinline__ void mom_diff(double a, double ax, double ay, double 
   }
 }
 
-// ------------------------------------------------------------------ one step
+// ------------------------------------------------------------------ track records
+
+struct Track {
+  int sp, vol;
+  double x, y, z, u, v, w, T, nlam;
+  uint32_t k0, k1, k2, evt, nstep, src;
+};
 
 struct Sec {
   int sp;
@@ -338,12 +344,12 @@ struct Sec {
   uint32_t k0, k1, k2;
 };
 
-struct StepOut {
+// Products of an interaction: up to three secondaries and the local deposit.
+struct Emit {
   int nsec;
   Sec s0, s1, s2;
-  bool alive;
-  double dep, esc, killed, step_len;
-  int n_pair, n_annih, limiter, process, escaped;
+  double dep;
+  int n_pair, n_annih;
 };
 
 // Append a secondary.  Written as per-field value selects (not a branch on which
@@ -360,7 +366,7 @@ __device__ __forceinline__ void put(Sec& r, bool on, int sp, double T, double u,
   r.k2 = on ? k2 : r.k2;
 }
 
-__device__ __forceinline__ void push(StepOut& o, int sp, double T, double u, double v, double w,
+__device__ __forceinline__ void push(Emit& o, int sp, double T, double u, double v, double w,
                                      uint32_t k0, uint32_t k1, uint32_t k2) {
   const int n = o.nsec;
   put(o.s0, n == 0, sp, T, u, v, w, k0, k1, k2);
@@ -369,17 +375,11 @@ __device__ __forceinline__ void push(StepOut& o, int sp, double T, double u, dou
   o.nsec = n + 1;
 }
 
-struct Track {
-  int sp, vol;
-  double x, y, z, u, v, w, T, nlam;
-  uint32_t k0, k1, k2, evt, nstep;
-};
-
 // Two back-to-back photons of m c^2, isotropic, from the positron's stream at
 // step 0xFFFFFFFF (draw 0 -> cos theta = 2u-1, draw 1 -> phi = 2 pi u).
 template <class R>
-__device__ __forceinline__ void annihilate_at_rest(const Params& P, StepOut& o, uint32_t p0, uint32_t p1,
-                                   uint32_t p2) {
+__device__ __forceinline__ void annihilate_at_rest(const Params& P, Emit& o, uint32_t p0,
+                                                   uint32_t p1, uint32_t p2) {
   Stream st;
   st.init(p0, p1, p2, kRestStep, P.seed);
   const R c = R(2) * Px<R>::uni(st.word(0)) - R(1);
@@ -397,10 +397,12 @@ __device__ __forceinline__ void annihilate_at_rest(const Params& P, StepOut& o, 
   push(o, EMS_GAMMA, kMe, -du, -dv, -cd, a, b, d);
 }
 
-// A secondary from an interaction of the parent at (its pre-increment) step.
+// A secondary from an interaction of the parent at its (pre-increment) step:
+// tracked at or above the tracking cut, else deposited (a positron then
+// annihilates at rest).
 template <class R>
-__device__ __forceinline__ void emit(const Params& P, StepOut& o, const Track& t, int sp,
-                                     double T, double u, double v, double w, uint32_t ordinal) {
+__device__ __forceinline__ void emit(const Params& P, Emit& o, const Track& t, int sp, double T,
+                                     double u, double v, double w, uint32_t ordinal) {
   uint32_t a, b, d;
   child_key(P.seed, t.k0, t.k1, t.k2, t.nstep, ordinal, a, b, d);
   const bool charged = sp != EMS_GAMMA;
@@ -412,15 +414,27 @@ __device__ __forceinline__ void emit(const Params& P, StepOut& o, const Track& t
   if (sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, a, b, d);
 }
 
-// One step of an alive track (see the file header for the order of operations).
+// ------------------------------------------------------------------ transport part
+
+struct Moved {
+  double dep, esc, killed, step_len;
+  int limiter, process, escaped;
+  int dest;  // -1 survives, -2 dead, >= 0 queue of its interaction
+};
+
+// The part of a step before the interaction: interaction length, cross sections,
+// step limits, distance to boundary, move, continuous loss, boundary crossing or
+// escape, process selection (u_1 against Sigma_i(T')), cutoffs.  A track whose
+// step ends in an interaction (or a positron that stops) is sent to a queue with
+// its step count not yet incremented; every other survivor's count is incremented.
 template <class R>
-__device__ __forceinline__ void step_track(const Params& P, Track& t, StepOut& o) {
+__device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   const double INF = HUGE_VAL;
   const int sp = t.sp;
   const int m = P.vmat[t.vol];
-  const bool matter = m >= 0 && !P.mat[m < 0 ? 0 : m].vacuum;
-  const bool charged = sp != EMS_GAMMA;
   const int mm = m < 0 ? 0 : m;
+  const bool matter = m >= 0 && !P.mat[mm].vacuum;
+  const bool charged = sp != EMS_GAMMA;
   Stream st;
   st.init(t.k0, t.k1, t.k2, t.nstep, P.seed);
 
@@ -491,19 +505,17 @@ __device__ __forceinline__ void step_track(const Params& P, Track& t, StepOut& o
   if (lim != 1 && sigtot > R(0)) t.nlam -= s * (double)sigtot;
   t.T = T1;
 
-  bool alive = true;
+  o.dest = -1;
   if (stopped) {
-    alive = false;
-    if (sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
+    o.dest = sp == EMS_POSITRON ? kQRest : -2;
   } else if (charged && T1 < P.tcut) {
     o.dep += T1;
-    alive = false;
-    if (sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
+    o.dest = sp == EMS_POSITRON ? kQRest : -2;
   } else if (lim == 0) {
     if (next < 0) {
       o.esc += T1;
       o.escaped = 1;
-      alive = false;
+      o.dest = -2;
     } else {
       t.vol = next;
     }
@@ -524,168 +536,191 @@ __device__ __forceinline__ void step_track(const Params& P, Track& t, StepOut& o
       else if (target < x0 + x1 + x2) p = 2;
       else p = x2 > R(0) ? 2 : (x1 > R(0) ? 1 : 0);
       o.process = p;
-      uint32_t d = 2;  // draw cursor of the interaction
-      const MatParams& M = P.mat[mm];
-      if (sp == EMS_GAMMA) {
-        const double E = T1;
-        if (p == 0) {  // Compton, 1/eps envelope
-          const R k = (R)(E / kMe);
-          const R leps0 = -Px<R>::lg(R(1) + R(2) * k);
-          R e = R(1), c = R(1);
-          for (int tr = 0; tr < kMaxTrial; ++tr) {
-            const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-            d += 2;
-            e = Px<R>::ex(ua * leps0);
-            c = R(1) - Px<R>::dv(R(1) - e, k * e);
-            const R s2 = (R(1) - c) * (R(1) + c);
-            if (ub < (R(1) + e * e - e * s2) * R(0.5)) break;
-          }
-          R sphi, cphi;
-          Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
-          const double E1 = (double)e * E;
-          const double Te = E - E1;
-          double du, dv, dw, eu, ev, ew;
-          rotate(t.u, t.v, t.w, (double)c, (double)cphi, (double)sphi, du, dv, dw);
-          mom_diff(E, t.u, t.v, t.w, E1, du, dv, dw, eu, ev, ew);
-          if (E1 >= P.tcut) {
-            t.T = E1;
-            t.u = du;
-            t.v = dv;
-            t.w = dw;
-          } else {
-            o.dep += E1;
-            alive = false;
-          }
-          emit<R>(P, o, t, EMS_ELECTRON, Te, eu, ev, ew, 0);
-        } else if (p == 1) {  // photoelectric: electron along the photon
-          alive = false;
-          emit<R>(P, o, t, EMS_ELECTRON, E, t.u, t.v, t.w, 0);
-        } else {  // pair
-          const R a = (R)(kMe / E);
-          R x = R(0.5);
-          for (int tr = 0; tr < kMaxTrial; ++tr) {
-            const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-            d += 2;
-            x = a + (R(1) - R(2) * a) * ua;
-            if (ub < R(1) - R(4.0 / 3.0) * x * (R(1) - x)) break;
-          }
-          const double Tm = (double)x * E - kMe;
-          const double Tp = (E - 2.0 * kMe) - Tm;
-          alive = false;
-          o.n_pair += 1;
-          emit<R>(P, o, t, EMS_ELECTRON, Tm, t.u, t.v, t.w, 0);
-          emit<R>(P, o, t, EMS_POSITRON, Tp, t.u, t.v, t.w, 1);
-        }
-      } else {
-        const R TR = (R)T1;
-        if (p == 0) {  // Moller / Bhabha, 1/eps^2 envelope
-          const R g = (R)(T1 / kMe + 1.0);
-          const R xi = (R)(T1 / M.Tc);
-          R e = R(0.5);
-          if (sp == EMS_ELECTRON) {
-            const R cc = Px<R>::dv(R(2) * g - R(1), g * g);
-            const R rr = Px<R>::dv(g - R(1), g);
-            const R norm = Px<R>::dv(R(4) * g * g, R(9) * g * g - R(10) * g + R(5));
-            for (int tr = 0; tr < kMaxTrial; ++tr) {
-              const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-              d += 2;
-              e = Px<R>::dv(R(1), xi - ua * (xi - R(2)));
-              const R om = R(1) - e;
-              const R f = rr * rr + Px<R>::dv(R(1), e * e) - Px<R>::dv(cc, e) +
-                          Px<R>::dv(R(1), om * om) - Px<R>::dv(cc, om);
-              if (ub < e * e * f * norm) break;
-            }
-          } else {
-            const R b2 = R(1) - Px<R>::dv(R(1), g * g);
-            const R y = Px<R>::dv(R(1), g + R(1));
-            const R h = R(1) - R(2) * y;
-            const R B1 = R(2) - y * y, B2 = h * (R(3) + y * y), B4 = h * h * h, B3 = B4 + h * h;
-            for (int tr = 0; tr < kMaxTrial; ++tr) {
-              const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-              d += 2;
-              e = Px<R>::dv(R(1), xi - ua * (xi - R(1)));
-              const R f = Px<R>::dv(R(1), b2 * e * e) - Px<R>::dv(B1, e) + B2 - B3 * e + B4 * e * e;
-              if (ub < b2 * e * e * f) break;
-            }
-          }
-          R sphi, cphi;
-          Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
-          const double Td = (double)e * T1;
-          const double Tp = T1 - Td;
-          const double cd = fmin(sqrt(Td * (T1 + 2.0 * kMe) / (T1 * (Td + 2.0 * kMe))), 1.0);
-          double du, dv, dw, pu, pv, pw;
-          rotate(t.u, t.v, t.w, cd, (double)cphi, (double)sphi, du, dv, dw);
-          const double P1 = sqrt(T1 * (T1 + 2.0 * kMe)), Pd = sqrt(Td * (Td + 2.0 * kMe));
-          mom_diff(P1, t.u, t.v, t.w, Pd, du, dv, dw, pu, pv, pw);
-          t.T = Tp;
-          t.u = pu;
-          t.v = pv;
-          t.w = pw;
-          if (Tp < P.tcut) {
-            o.dep += Tp;
-            alive = false;
-            if (sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
-          }
-          emit<R>(P, o, t, EMS_ELECTRON, Td, du, dv, dw, 0);
-        } else if (p == 1) {  // bremsstrahlung, 1/k envelope; photon along the parent
-          const double kc = M.kc;
-          const R L = Px<R>::lg((R)(T1 / kc));
-          R k = (R)kc;
-          for (int tr = 0; tr < kMaxTrial; ++tr) {
-            const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-            d += 2;
-            k = (R)kc * Px<R>::ex(ua * L);
-            const R y = Px<R>::dv(k, TR);
-            if (ub < R(1) - y + R(0.75) * y * y) break;
-          }
-          const double kd = (double)k;
-          const double Tp = T1 - kd;
-          t.T = Tp;
-          if (Tp < P.tcut) {
-            o.dep += Tp;
-            alive = false;
-            if (sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
-          }
-          emit<R>(P, o, t, EMS_GAMMA, kd, t.u, t.v, t.w, 0);
-        } else {  // annihilation in flight, 1/eps envelope
-          const R g = (R)(T1 / kMe + 1.0);
-          const R emin = R(0.5) * (R(1) - Px<R>::sq(Px<R>::dv(g - R(1), g + R(1))));
-          const R L = Px<R>::lg(Px<R>::dv(R(1) - emin, emin));
-          const R A = g * g + R(4) * g + R(1), norm = g * g + R(2) * g - R(1);
-          R e = R(0.5);
-          for (int tr = 0; tr < kMaxTrial; ++tr) {
-            const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
-            d += 2;
-            e = emin * Px<R>::ex(ua * L);
-            const R S = -(g + R(1)) * (g + R(1)) + Px<R>::dv(A, e) - Px<R>::dv(R(1), e * e);
-            if (ub < Px<R>::dv(e * S, norm)) break;
-          }
-          R sphi, cphi;
-          Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
-          const double gd = T1 / kMe + 1.0;
-          const double Etot = T1 + 2.0 * kMe;
-          const double E1 = (double)e * Etot;
-          const double E2 = Etot - E1;
-          const double ed = (double)e;
-          const double c1 = fmin(fmax((ed * (gd + 1.0) - 1.0) / (ed * sqrt(gd * gd - 1.0)), -1.0), 1.0);
-          double au, av, aw, bu, bv, bw;
-          rotate(t.u, t.v, t.w, c1, (double)cphi, (double)sphi, au, av, aw);
-          const double Pp = sqrt(T1 * (T1 + 2.0 * kMe));
-          mom_diff(Pp, t.u, t.v, t.w, E1, au, av, aw, bu, bv, bw);
-          alive = false;
-          o.n_annih += 1;
-          emit<R>(P, o, t, EMS_GAMMA, E1, au, av, aw, 0);
-          emit<R>(P, o, t, EMS_GAMMA, E2, bu, bv, bw, 1);
-        }
-      }
+      if (sp == EMS_GAMMA) o.dest = p;  // Compton, photoelectric, pair
+      else if (p == 0) o.dest = sp == EMS_ELECTRON ? kQMoller : kQBhabha;
+      else if (p == 1) o.dest = kQBrems;
+      else o.dest = kQAnnihilation;
     }
   }
-  t.nstep += 1;
-  if (alive && t.nstep >= P.max_steps) {
-    o.killed += t.T;
-    alive = false;
+  if (o.dest == -1) {
+    t.nstep += 1;
+    if (t.nstep >= P.max_steps) {
+      o.killed += t.T;
+      o.dest = -2;
+    }
   }
-  o.alive = alive;
+}
+
+// ------------------------------------------------------------------ interactions
+
+// The interaction of queue q (uniform over a block) for a track at its post-step
+// state; draws from u_2 on.  On return the parent's step count is incremented and
+// `alive` says whether it survives.
+template <class R>
+__device__ __forceinline__ void interact(const Params& P, int q, Track& t, Emit& o, bool& alive) {
+  alive = true;
+  if (q == kQRest) {
+    alive = false;
+    annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
+    t.nstep += 1;
+    return;
+  }
+  const int mm = P.vmat[t.vol] < 0 ? 0 : P.vmat[t.vol];
+  const MatParams& M = P.mat[mm];
+  Stream st;
+  st.init(t.k0, t.k1, t.k2, t.nstep, P.seed);
+  uint32_t d = 2;  // draw cursor of the interaction
+  const double T1 = t.T;
+  if (q == kQCompton) {  // 1/eps envelope
+    const double E = T1;
+    const R k = (R)(E / kMe);
+    const R leps0 = -Px<R>::lg(R(1) + R(2) * k);
+    R e = R(1), c = R(1);
+    for (int tr = 0; tr < kMaxTrial; ++tr) {
+      const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+      d += 2;
+      e = Px<R>::ex(ua * leps0);
+      c = R(1) - Px<R>::dv(R(1) - e, k * e);
+      const R s2 = (R(1) - c) * (R(1) + c);
+      if (ub < (R(1) + e * e - e * s2) * R(0.5)) break;
+    }
+    R sphi, cphi;
+    Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
+    const double E1 = (double)e * E;
+    const double Te = E - E1;
+    double du, dv, dw, eu, ev, ew;
+    rotate(t.u, t.v, t.w, (double)c, (double)cphi, (double)sphi, du, dv, dw);
+    mom_diff(E, t.u, t.v, t.w, E1, du, dv, dw, eu, ev, ew);
+    if (E1 >= P.tcut) {
+      t.T = E1;
+      t.u = du;
+      t.v = dv;
+      t.w = dw;
+    } else {
+      o.dep += E1;
+      alive = false;
+    }
+    emit<R>(P, o, t, EMS_ELECTRON, Te, eu, ev, ew, 0);
+  } else if (q == kQPhoto) {  // electron along the photon
+    alive = false;
+    emit<R>(P, o, t, EMS_ELECTRON, T1, t.u, t.v, t.w, 0);
+  } else if (q == kQPair) {
+    const double E = T1;
+    const R a = (R)(kMe / E);
+    R x = R(0.5);
+    for (int tr = 0; tr < kMaxTrial; ++tr) {
+      const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+      d += 2;
+      x = a + (R(1) - R(2) * a) * ua;
+      if (ub < R(1) - R(4.0 / 3.0) * x * (R(1) - x)) break;
+    }
+    const double Tm = (double)x * E - kMe;
+    const double Tp = (E - 2.0 * kMe) - Tm;
+    alive = false;
+    o.n_pair += 1;
+    emit<R>(P, o, t, EMS_ELECTRON, Tm, t.u, t.v, t.w, 0);
+    emit<R>(P, o, t, EMS_POSITRON, Tp, t.u, t.v, t.w, 1);
+  } else if (q == kQMoller || q == kQBhabha) {  // 1/eps^2 envelope
+    const R g = (R)(T1 / kMe + 1.0);
+    const R xi = (R)(T1 / M.Tc);
+    R e = R(0.5);
+    if (q == kQMoller) {
+      const R cc = Px<R>::dv(R(2) * g - R(1), g * g);
+      const R rr = Px<R>::dv(g - R(1), g);
+      const R norm = Px<R>::dv(R(4) * g * g, R(9) * g * g - R(10) * g + R(5));
+      for (int tr = 0; tr < kMaxTrial; ++tr) {
+        const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+        d += 2;
+        e = Px<R>::dv(R(1), xi - ua * (xi - R(2)));
+        const R om = R(1) - e;
+        const R f = rr * rr + Px<R>::dv(R(1), e * e) - Px<R>::dv(cc, e) +
+                    Px<R>::dv(R(1), om * om) - Px<R>::dv(cc, om);
+        if (ub < e * e * f * norm) break;
+      }
+    } else {
+      const R b2 = R(1) - Px<R>::dv(R(1), g * g);
+      const R y = Px<R>::dv(R(1), g + R(1));
+      const R h = R(1) - R(2) * y;
+      const R B1 = R(2) - y * y, B2 = h * (R(3) + y * y), B4 = h * h * h, B3 = B4 + h * h;
+      for (int tr = 0; tr < kMaxTrial; ++tr) {
+        const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+        d += 2;
+        e = Px<R>::dv(R(1), xi - ua * (xi - R(1)));
+        const R f = Px<R>::dv(R(1), b2 * e * e) - Px<R>::dv(B1, e) + B2 - B3 * e + B4 * e * e;
+        if (ub < b2 * e * e * f) break;
+      }
+    }
+    R sphi, cphi;
+    Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
+    const double Td = (double)e * T1;
+    const double Tp = T1 - Td;
+    const double cd = fmin(sqrt(Td * (T1 + 2.0 * kMe) / (T1 * (Td + 2.0 * kMe))), 1.0);
+    double du, dv, dw, pu, pv, pw;
+    rotate(t.u, t.v, t.w, cd, (double)cphi, (double)sphi, du, dv, dw);
+    const double P1 = sqrt(T1 * (T1 + 2.0 * kMe)), Pd = sqrt(Td * (Td + 2.0 * kMe));
+    mom_diff(P1, t.u, t.v, t.w, Pd, du, dv, dw, pu, pv, pw);
+    t.T = Tp;
+    t.u = pu;
+    t.v = pv;
+    t.w = pw;
+    if (Tp < P.tcut) {
+      o.dep += Tp;
+      alive = false;
+      if (t.sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
+    }
+    emit<R>(P, o, t, EMS_ELECTRON, Td, du, dv, dw, 0);
+  } else if (q == kQBrems) {  // 1/k envelope; photon along the parent
+    const double kc = M.kc;
+    const R TR = (R)T1;
+    const R L = Px<R>::lg((R)(T1 / kc));
+    R k = (R)kc;
+    for (int tr = 0; tr < kMaxTrial; ++tr) {
+      const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+      d += 2;
+      k = (R)kc * Px<R>::ex(ua * L);
+      const R y = Px<R>::dv(k, TR);
+      if (ub < R(1) - y + R(0.75) * y * y) break;
+    }
+    const double kd = (double)k;
+    const double Tp = T1 - kd;
+    t.T = Tp;
+    if (Tp < P.tcut) {
+      o.dep += Tp;
+      alive = false;
+      if (t.sp == EMS_POSITRON) annihilate_at_rest<R>(P, o, t.k0, t.k1, t.k2);
+    }
+    emit<R>(P, o, t, EMS_GAMMA, kd, t.u, t.v, t.w, 0);
+  } else {  // annihilation in flight, 1/eps envelope
+    const R g = (R)(T1 / kMe + 1.0);
+    const R emin = R(0.5) * (R(1) - Px<R>::sq(Px<R>::dv(g - R(1), g + R(1))));
+    const R L = Px<R>::lg(Px<R>::dv(R(1) - emin, emin));
+    const R A = g * g + R(4) * g + R(1), norm = g * g + R(2) * g - R(1);
+    R e = R(0.5);
+    for (int tr = 0; tr < kMaxTrial; ++tr) {
+      const R ua = Px<R>::uni(st.word(d)), ub = Px<R>::uni(st.word(d + 1));
+      d += 2;
+      e = emin * Px<R>::ex(ua * L);
+      const R S = -(g + R(1)) * (g + R(1)) + Px<R>::dv(A, e) - Px<R>::dv(R(1), e * e);
+      if (ub < Px<R>::dv(e * S, norm)) break;
+    }
+    R sphi, cphi;
+    Px<R>::sc(R(kTwoPi) * Px<R>::uni(st.word(d)), &sphi, &cphi);
+    const double gd = T1 / kMe + 1.0;
+    const double Etot = T1 + 2.0 * kMe;
+    const double E1 = (double)e * Etot;
+    const double E2 = Etot - E1;
+    const double ed = (double)e;
+    const double c1 = fmin(fmax((ed * (gd + 1.0) - 1.0) / (ed * sqrt(gd * gd - 1.0)), -1.0), 1.0);
+    double au, av, aw, bu, bv, bw;
+    rotate(t.u, t.v, t.w, c1, (double)cphi, (double)sphi, au, av, aw);
+    const double Pp = sqrt(T1 * (T1 + 2.0 * kMe));
+    mom_diff(Pp, t.u, t.v, t.w, E1, au, av, aw, bu, bv, bw);
+    alive = false;
+    o.n_annih += 1;
+    emit<R>(P, o, t, EMS_GAMMA, E1, au, av, aw, 0);
+    emit<R>(P, o, t, EMS_GAMMA, E2, bu, bv, bw, 1);
+  }
+  t.nstep += 1;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -714,25 +749,52 @@ __device__ __forceinline__ void write_track(const Pool& p, uint32_t j, int sp, i
   p.meta[j] = (uint32_t)sp | ((uint32_t)vol << 2);
 }
 
+// write_track into one of two pools chosen per lane (a branch, not a select of
+// pool descriptors, which would be spilled)
+__device__ __forceinline__ void write_either(bool g, const Pool& pg, const Pool& pc, uint32_t j,
+                                             int sp, int vol, double x, double y, double z,
+                                             double u, double v, double w, double T, double nlam,
+                                             uint32_t k0, uint32_t k1, uint32_t k2, uint32_t evt,
+                                             uint32_t nstep) {
+  if (g) write_track(pg, j, sp, vol, x, y, z, u, v, w, T, nlam, k0, k1, k2, evt, nstep);
+  else write_track(pc, j, sp, vol, x, y, z, u, v, w, T, nlam, k0, k1, k2, evt, nstep);
+}
+
 __device__ __forceinline__ unsigned long long fixed_point(double e, double scale) {
   return (unsigned long long)llrint(e * scale);
 }
 
-// One step iteration: tracks [0, n_in) of `in`; the first n_step are stepped,
-// the rest are copied unchanged (deferred for lack of output room).  Outputs are
-// appended to `out` at counters[0].
+__device__ __forceinline__ void count_done(const Params& P, uint32_t e, int delta) {
+  if (delta == 0) return;
+  const int old = atomicAdd(&P.alive[e], delta);
+  if (old + delta == 0) {
+    const uint32_t k = atomicAdd(&P.counters[kCDone], 1u);
+    if (k < P.max_events) P.done[k] = e;
+  }
+}
+
+// One iteration, part 1.  Blocks [0, nbG) step the photon pool, the rest the
+// charged pool (so every wavefront holds one species class).  In each pool the
+// first k tracks are stepped and the rest copied unchanged (deferred for lack of
+// output room).  Survivors go to the output pool of their class, tracks that
+// interact to their process queue; both are allocated one atomic per wavefront.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_step(Params P, Pool in, Pool out, uint32_t n_in,
-                                                 uint32_t n_step, ems_step_record* rec) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool inC, uint32_t nG,
+                                                      uint32_t kG, uint32_t nC, uint32_t kC,
+                                                      uint32_t nbG, Pool outG, Pool outC,
+                                                      IQueue Q, ems_step_record* rec) {
+  const bool cblk = blockIdx.x >= nbG;
+  const Pool& in = cblk ? inC : inG;
+  const Pool& out = cblk ? outC : outG;
+  const uint32_t n = cblk ? nC : nG, k = cblk ? kC : kG;
+  const uint32_t i = (blockIdx.x - (cblk ? nbG : 0u)) * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  const bool valid = i < n_in;
+  const bool valid = i < n;
   Track t{};
-  StepOut o{};
+  Moved o{};
   o.process = -1;
-  bool stepped = false, keep = false;
-  int vol_out = 0;
-  bool usable = valid;
+  o.dest = -2;
+  bool stepped = false, usable = valid, vol_out = false;
   uint32_t vol = 0;
   if (valid) {
     const uint32_t meta = in.meta[i];
@@ -755,109 +817,282 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P, Pool in, Pool out, ui
     t.k1 = in.k1[i];
     t.k2 = in.k2[i];
     t.nstep = in.nstep[i];
+    t.src = rec ? in.src[i] : 0u;
     if (vol == kVolOut) {  // primary born outside the world: escapes with no step
+      vol_out = true;
       t.vol = 0;
       o.esc = t.T;
       o.escaped = 1;
-      o.alive = false;
-      stepped = false;
-      keep = false;
-      vol_out = 1;
-    } else if (i < n_step) {
-      t.vol = (int)vol;
-      step_track<R>(P, t, o);
-      stepped = true;
-      keep = o.alive;
     } else {
       t.vol = (int)vol;
-      keep = true;
-    }
-  }
-  const int dep_vol_bin = (usable && !vol_out) ? P.vbin[(int)vol] : 0;
-
-  // ---- wave-aggregated allocation of output slots
-  const uint64_t mP = __ballot(keep);
-  const uint64_t m0 = __ballot(o.nsec > 0);
-  const uint64_t m1 = __ballot(o.nsec > 1);
-  const uint64_t m2 = __ballot(o.nsec > 2);
-  const uint32_t cP = (uint32_t)__popcll(mP), c0 = (uint32_t)__popcll(m0),
-                 c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
-  const uint32_t total = cP + c0 + c1 + c2;
-  uint32_t base = 0;
-  if (lane == 0 && total) base = atomicAdd(&P.counters[0], total);
-  base = __shfl(base, 0);
-  if (keep)
-    write_track(out, base + lanes_below(mP, lane), t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T,
-                t.nlam, t.k0, t.k1, t.k2, t.evt, t.nstep);
-  if (o.nsec > 0)
-    write_track(out, base + cP + lanes_below(m0, lane), o.s0.sp, t.vol, t.x, t.y, t.z, o.s0.u,
-                o.s0.v, o.s0.w, o.s0.T, -1.0, o.s0.k0, o.s0.k1, o.s0.k2, t.evt, 0);
-  if (o.nsec > 1)
-    write_track(out, base + cP + c0 + lanes_below(m1, lane), o.s1.sp, t.vol, t.x, t.y, t.z,
-                o.s1.u, o.s1.v, o.s1.w, o.s1.T, -1.0, o.s1.k0, o.s1.k1, o.s1.k2, t.evt, 0);
-  if (o.nsec > 2)
-    write_track(out, base + cP + c0 + c1 + lanes_below(m2, lane), o.s2.sp, t.vol, t.x, t.y, t.z,
-                o.s2.u, o.s2.v, o.s2.w, o.s2.T, -1.0, o.s2.k0, o.s2.k1, o.s2.k2, t.evt, 0);
-
-  // ---- run counters: track-steps by species, one atomic per wave
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const uint64_t ms = __ballot(stepped && t.sp == s);
-    if (lane == 0 && ms) atomicAdd(&P.steps[s], (unsigned long long)__popcll(ms));
-  }
-
-  if (!usable) return;
-  // ---- tallies of the event slot
-  const uint32_t e = t.evt;
-  if (stepped || vol_out) {
-    const double sc = P.scale[e];
-    if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + dep_vol_bin], fixed_point(o.dep, sc));
-    if (o.esc > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 0], fixed_point(o.esc, sc));
-    if (o.killed > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(o.killed, sc));
-    if (o.n_pair) atomicAdd(&P.ledger[(size_t)e * kLedger + 2], (unsigned long long)o.n_pair);
-    if (o.n_annih) atomicAdd(&P.ledger[(size_t)e * kLedger + 3], (unsigned long long)o.n_annih);
-    if (o.escaped) {
-      const double tt = (log(o.esc) - P.lnE0) * P.inv_dlnE;
-      int b = !(tt > 0.0) ? 0 : (tt >= (double)(kGrid - 1) ? kGrid - 1 : (int)tt);
-      atomicAdd(&P.esc_hist[t.sp * kGrid + b], 1ull);
-    }
-    const int delta = (keep ? 1 : 0) + o.nsec - 1;
-    if (delta != 0) {
-      const int old = atomicAdd(&P.alive[e], delta);
-      if (old + delta == 0) {
-        const uint32_t k = atomicAdd(&P.counters[1], 1u);
-        if (k < P.max_events) P.done[k] = e;
+      if (i < k) {
+        transport<R>(P, t, o);
+        stepped = true;
+      } else {
+        o.dest = -1;  // deferred: copied unchanged
       }
     }
   }
-  if (rec && i < n_step) {
-    ems_step_record r;
+
+  // ---- block-level reservation: stream 0 survivors (output pool of this class),
+  // 1..8 process queues, 9..11 track-steps by species; one atomic per block and stream
+  constexpr int kW = kBlock / 64, kS = 12;
+  __shared__ uint32_t sh_cnt[kW][kS];
+  __shared__ uint32_t sh_base[kS];
+  const int wave = threadIdx.x >> 6;
+  const uint64_t mS = __ballot(o.dest == -1);
+  uint64_t mq[kNumQueues];
+#pragma unroll
+  for (int q = 0; q < kNumQueues; ++q) mq[q] = __ballot(o.dest == q);
+  uint64_t mst[3];
+#pragma unroll
+  for (int sp = 0; sp < 3; ++sp) mst[sp] = __ballot(stepped && t.sp == sp);
+  if (lane == 0) {
+    sh_cnt[wave][0] = (uint32_t)__popcll(mS);
+#pragma unroll
+    for (int q = 0; q < kNumQueues; ++q) sh_cnt[wave][1 + q] = (uint32_t)__popcll(mq[q]);
+#pragma unroll
+    for (int sp = 0; sp < 3; ++sp) sh_cnt[wave][9 + sp] = (uint32_t)__popcll(mst[sp]);
+  }
+  __syncthreads();
+  if (threadIdx.x < kS) {
+    const int st = threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kW; ++w2) tot += sh_cnt[w2][st];
+    uint32_t b0 = 0;
+    if (st == 0) {
+      if (tot) b0 = atomicAdd(&P.counters[cblk ? kCOutC : kCOutG], tot);
+    } else if (st < 9) {
+      if (tot) b0 = atomicAdd(&P.counters[kCQueue + st - 1], tot);
+    } else if (tot) {
+      atomicAdd(&P.steps[st - 9], (unsigned long long)tot);
+    }
+    sh_base[st] = b0;
+  }
+  __syncthreads();
+  if (o.dest == -1) {
+    uint32_t j = sh_base[0] + lanes_below(mS, lane);
+    for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][0];
+    write_track(out, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, t.nlam, t.k0, t.k1, t.k2,
+                t.evt, t.nstep);
+    if (rec) out.src[j] = t.src;
+  } else if (o.dest >= 0) {  // interacting track -> its process queue
+    const int q = o.dest;
+    uint64_t own = mq[0];
+#pragma unroll
+    for (int q2 = 1; q2 < kNumQueues; ++q2) own = q == q2 ? mq[q2] : own;
+    uint32_t j = sh_base[1 + q] + lanes_below(own, lane);
+    for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][1 + q];
+    j += (uint32_t)q * Q.capacity;
+    Q.x[j] = t.x;
+    Q.y[j] = t.y;
+    Q.z[j] = t.z;
+    Q.u[j] = t.u;
+    Q.v[j] = t.v;
+    Q.w[j] = t.w;
+    Q.T[j] = t.T;
+    Q.k0[j] = t.k0;
+    Q.k1[j] = t.k1;
+    Q.k2[j] = t.k2;
+    Q.evt[j] = t.evt;
+    Q.nstep[j] = t.nstep;
+    Q.meta[j] = (uint32_t)t.sp | ((uint32_t)t.vol << 2);
+    Q.src[j] = t.src;
+  }
+  if (!usable || !(stepped || vol_out)) return;
+  // ---- tallies of the event slot (deposits are scored in the pre-step volume)
+  const uint32_t e = t.evt;
+  const double sc = P.scale[e];
+  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + P.vbin[vol_out ? 0 : (int)vol]],
+                             fixed_point(o.dep, sc));
+  if (o.esc > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 0], fixed_point(o.esc, sc));
+  if (o.killed > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(o.killed, sc));
+  if (o.escaped) {
+    const double tt = (log(o.esc) - P.lnE0) * P.inv_dlnE;
+    const int b = !(tt > 0.0) ? 0 : (tt >= (double)(kGrid - 1) ? kGrid - 1 : (int)tt);
+    atomicAdd(&P.esc_hist[t.sp * kGrid + b], 1ull);
+  }
+  if (o.dest == -2) count_done(P, e, -1);
+  if (rec && stepped) {
+    ems_step_record& r = rec[t.src];
     r.dep = o.dep;
     r.esc = o.esc;
     r.killed = o.killed;
     r.step_len = o.step_len;
     r.limiter = o.limiter;
     r.process = o.process;
-    r.n_pair = o.n_pair;
-    r.n_annih = o.n_annih;
-    r.n_out = (keep ? 1 : 0) + o.nsec;
+    r.n_pair = 0;
+    r.n_annih = 0;
+    r.n_out = o.dest == -1 ? 1 : 0;
     r.escaped = o.escaped;
-    rec[i] = r;
   }
 }
 
-// Admit queued primaries: ring entries [head, head + m) -> pool slots [n0, n0 + m).
-__global__ void k_admit(Params P, Queue q, Pool pool, uint32_t head, uint32_t m, uint32_t n0) {
+// Wave-aggregated append of one output stream (parent or secondary j) into the
+// two class pools: per class a ballot, a rank and one atomic per wavefront.
+struct OutBase {
+  uint32_t g, c;
+};
+
+// One iteration, part 2: the interactions.  Blocks are partitioned among the
+// queues (block-uniform process, so a wavefront runs one sampler); survivors and
+// secondaries go to the output pool of their class.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool outG, Pool outC,
+                                                     ems_step_record* rec) {
+  // block -> (queue, block within queue) from the queue sizes
+  uint32_t start = 0, qsel = kNumQueues, cnt = 0;
+#pragma unroll
+  for (int q = 0; q < kNumQueues; ++q) {
+    const uint32_t c = P.counters[kCQueue + q];
+    const uint32_t nb = (c + kBlock - 1) / kBlock;
+    if (qsel == kNumQueues && blockIdx.x < start + nb) {
+      qsel = q;
+      cnt = c;
+    } else if (qsel == kNumQueues) {
+      start += nb;
+    }
+  }
+  if (qsel == kNumQueues) return;  // whole block beyond the work
+  const int q = (int)qsel;
+  const uint32_t i = (blockIdx.x - start) * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < cnt;
+  Track t{};
+  Emit o{};
+  bool alive = false, looped = false;
+  if (valid) {
+    const uint32_t j = q * Q.capacity + i;
+    t.x = Q.x[j];
+    t.y = Q.y[j];
+    t.z = Q.z[j];
+    t.u = Q.u[j];
+    t.v = Q.v[j];
+    t.w = Q.w[j];
+    t.T = Q.T[j];
+    t.k0 = Q.k0[j];
+    t.k1 = Q.k1[j];
+    t.k2 = Q.k2[j];
+    t.evt = Q.evt[j];
+    t.nstep = Q.nstep[j];
+    const uint32_t meta = Q.meta[j];
+    t.sp = (int)(meta & 3u);
+    t.vol = (int)(meta >> 2);
+    t.src = Q.src[j];
+    t.nlam = -1.0;
+    interact<R>(P, q, t, o, alive);
+    if (alive && t.nstep >= P.max_steps) {  // looper cap after the interaction
+      alive = false;
+      looped = true;
+    }
+  }
+  // ---- outputs: stream 0 = parent, 1..3 = secondaries, each to its class pool
+  const bool h0 = alive, h1 = o.nsec > 0, h2 = o.nsec > 1, h3 = o.nsec > 2;
+  const bool g0 = t.sp == EMS_GAMMA, g1 = o.s0.sp == EMS_GAMMA, g2 = o.s1.sp == EMS_GAMMA,
+             g3 = o.s2.sp == EMS_GAMMA;
+  const uint64_t mg0 = __ballot(h0 && g0), mc0 = __ballot(h0 && !g0);
+  const uint64_t mg1 = __ballot(h1 && g1), mc1 = __ballot(h1 && !g1);
+  const uint64_t mg2 = __ballot(h2 && g2), mc2 = __ballot(h2 && !g2);
+  const uint64_t mg3 = __ballot(h3 && g3), mc3 = __ballot(h3 && !g3);
+  const uint32_t ng0 = __popcll(mg0), ng1 = __popcll(mg1), ng2 = __popcll(mg2), ng3 = __popcll(mg3);
+  const uint32_t nc0 = __popcll(mc0), nc1 = __popcll(mc1), nc2 = __popcll(mc2), nc3 = __popcll(mc3);
+  // block-level reservation of the two output pools, one atomic per block and pool
+  constexpr int kW = kBlock / 64;
+  __shared__ uint32_t sh_cnt[kW][2];
+  __shared__ uint32_t sh_base[2];
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh_cnt[wave][0] = ng0 + ng1 + ng2 + ng3;
+    sh_cnt[wave][1] = nc0 + nc1 + nc2 + nc3;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kW; ++w2) tot += sh_cnt[w2][threadIdx.x];
+    sh_base[threadIdx.x] = tot ? atomicAdd(&P.counters[threadIdx.x == 0 ? kCOutG : kCOutC], tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t bg = sh_base[0], bc = sh_base[1];
+  for (int w2 = 0; w2 < wave; ++w2) {
+    bg += sh_cnt[w2][0];
+    bc += sh_cnt[w2][1];
+  }
+  if (h0) {
+    const uint32_t j = g0 ? bg + lanes_below(mg0, lane) : bc + lanes_below(mc0, lane);
+    write_either(g0, outG, outC, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, -1.0, t.k0,
+                t.k1, t.k2, t.evt, t.nstep);
+    if (rec) {
+      if (g0) outG.src[j] = t.src;
+      else outC.src[j] = t.src;
+    }
+  }
+  if (h1) {
+    const uint32_t j = g1 ? bg + ng0 + lanes_below(mg1, lane) : bc + nc0 + lanes_below(mc1, lane);
+    write_either(g1, outG, outC, j, o.s0.sp, t.vol, t.x, t.y, t.z, o.s0.u, o.s0.v, o.s0.w, o.s0.T,
+                -1.0, o.s0.k0, o.s0.k1, o.s0.k2, t.evt, 0u);
+  }
+  if (h2) {
+    const uint32_t j = g2 ? bg + ng0 + ng1 + lanes_below(mg2, lane)
+                          : bc + nc0 + nc1 + lanes_below(mc2, lane);
+    write_either(g2, outG, outC, j, o.s1.sp, t.vol, t.x, t.y, t.z, o.s1.u, o.s1.v, o.s1.w, o.s1.T,
+                -1.0, o.s1.k0, o.s1.k1, o.s1.k2, t.evt, 0u);
+  }
+  if (h3) {
+    const uint32_t j = g3 ? bg + ng0 + ng1 + ng2 + lanes_below(mg3, lane)
+                          : bc + nc0 + nc1 + nc2 + lanes_below(mc3, lane);
+    write_either(g3, outG, outC, j, o.s2.sp, t.vol, t.x, t.y, t.z, o.s2.u, o.s2.v, o.s2.w, o.s2.T,
+                -1.0, o.s2.k0, o.s2.k1, o.s2.k2, t.evt, 0u);
+  }
+  if (!valid) return;
+  const uint32_t e = t.evt;
+  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + P.vbin[t.vol]], fixed_point(o.dep, P.scale[e]));
+  if (o.n_pair) atomicAdd(&P.ledger[(size_t)e * kLedger + 2], (unsigned long long)o.n_pair);
+  if (o.n_annih) atomicAdd(&P.ledger[(size_t)e * kLedger + 3], (unsigned long long)o.n_annih);
+  if (looped) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(t.T, P.scale[e]));
+  count_done(P, e, (alive ? 1 : 0) + o.nsec - 1);
+  if (rec) {
+    ems_step_record& r = rec[t.src];
+    r.dep += o.dep;
+    r.n_pair = o.n_pair;
+    r.n_annih = o.n_annih;
+    r.n_out = (alive ? 1 : 0) + o.nsec;
+    if (looped) r.killed += t.T;
+  }
+}
+
+// Start of an iteration: clear the iteration counters and set the admission
+// cursors to the current pool sizes.
+__global__ void k_iter_begin(uint32_t* counters, uint32_t nG, uint32_t nC) {
+  const int j = threadIdx.x;
+  if (j < kNumCounters) counters[j] = j == kCAdmitG ? nG : (j == kCAdmitC ? nC : 0u);
+}
+
+// Admit queued primaries: ring entries [head, head + m) appended to the photon or
+// charged pool at the admission cursors (one atomic per wavefront and class).
+__global__ void k_admit(Params P, Queue q, Pool poolG, Pool poolC, uint32_t head, uint32_t m) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  const uint32_t r = (head + j) % q.capacity;
+  const int lane = threadIdx.x & 63;
+  const bool valid = j < m;
+  const uint32_t r = valid ? (head + j) % q.capacity : 0u;
+  const int sp = valid ? q.species[r] : 0;
+  const bool g = valid && sp == EMS_GAMMA, c = valid && sp != EMS_GAMMA;
+  const uint64_t mg = __ballot(g), mc = __ballot(c);
+  uint32_t bg = 0, bc = 0;
+  if (lane == 0 && mg) bg = atomicAdd(&P.counters[kCAdmitG], (uint32_t)__popcll(mg));
+  if (lane == 0 && mc) bc = atomicAdd(&P.counters[kCAdmitC], (uint32_t)__popcll(mc));
+  bg = __shfl(bg, 0);
+  bc = __shfl(bc, 0);
+  if (!valid) return;
   const double x = q.x[r], y = q.y[r], z = q.z[r], u = q.u[r], v = q.v[r], w = q.w[r];
-  uint32_t a, b, c, d;
-  philox10(q.event_id[r], q.index[r], 0u, 0u, P.seed, 0x243F6A88u, a, b, c, d);
+  uint32_t a, b, cc, d;
+  philox10(q.event_id[r], q.index[r], 0u, 0u, P.seed, 0x243F6A88u, a, b, cc, d);
   const int vol = locate(P, x, y, z, u, v, w);
-  const uint32_t k = n0 + j;
-  write_track(pool, k, q.species[r], 0, x, y, z, u, v, w, q.T[r], -1.0, a, b, c, q.slot[r], 0u);
-  pool.meta[k] = (uint32_t)q.species[r] | ((vol < 0 ? kVolOut : (uint32_t)vol) << 2);
+  const Pool& pool = g ? poolG : poolC;
+  const uint32_t k = g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane);
+  write_track(pool, k, sp, 0, x, y, z, u, v, w, q.T[r], -1.0, a, b, cc, q.slot[r], 0u);
+  pool.meta[k] = (uint32_t)sp | ((vol < 0 ? kVolOut : (uint32_t)vol) << 2);
 }
 
 // Copy a batch's primaries into the ring at tail; row r belongs to the event e with
@@ -939,32 +1174,47 @@ __global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
   if (j < n) p[j] = 0ull;
 }
 
-// Diagnostics: external SoA <-> pool layout.
-__global__ void k_pool_load(Pool p, ems_track_soa s, uint32_t n) {
+// Diagnostics: external SoA <-> pool layout (states sorted into the two class
+// pools at the admission cursors; src remembers the input index).
+__global__ void k_pool_load(Params P, Pool pg, Pool pc, ems_track_soa s, uint32_t n) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  write_track(p, j, s.species[j], s.vol[j], s.x[j], s.y[j], s.z[j], s.u[j], s.v[j], s.w[j],
-              s.T[j], s.nlam[j], s.k0[j], s.k1[j], s.k2[j], s.event[j], s.nstep[j]);
+  const int lane = threadIdx.x & 63;
+  const bool valid = j < n;
+  const int sp = valid ? s.species[j] : 0;
+  const bool g = valid && sp == EMS_GAMMA, c = valid && sp != EMS_GAMMA;
+  const uint64_t mg = __ballot(g), mc = __ballot(c);
+  uint32_t bg = 0, bc = 0;
+  if (lane == 0 && mg) bg = atomicAdd(&P.counters[kCAdmitG], (uint32_t)__popcll(mg));
+  if (lane == 0 && mc) bc = atomicAdd(&P.counters[kCAdmitC], (uint32_t)__popcll(mc));
+  bg = __shfl(bg, 0);
+  bc = __shfl(bc, 0);
+  if (!valid) return;
+  const Pool& p = g ? pg : pc;
+  const uint32_t k = g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane);
+  write_track(p, k, sp, s.vol[j], s.x[j], s.y[j], s.z[j], s.u[j], s.v[j], s.w[j], s.T[j],
+              s.nlam[j], s.k0[j], s.k1[j], s.k2[j], s.event[j], s.nstep[j]);
+  p.src[k] = j;
 }
 
-__global__ void k_pool_dump(Pool p, ems_track_soa s, uint32_t n) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  s.x[j] = p.x[j];
-  s.y[j] = p.y[j];
-  s.z[j] = p.z[j];
-  s.u[j] = p.u[j];
-  s.v[j] = p.v[j];
-  s.w[j] = p.w[j];
-  s.T[j] = p.T[j];
-  s.nlam[j] = p.nlam[j];
-  s.k0[j] = p.k0[j];
-  s.k1[j] = p.k1[j];
-  s.k2[j] = p.k2[j];
-  s.event[j] = p.evt[j];
-  s.nstep[j] = p.nstep[j];
-  s.species[j] = (int32_t)(p.meta[j] & 3u);
-  s.vol[j] = (int32_t)(p.meta[j] >> 2);
+__global__ void k_pool_dump(Pool p, ems_track_soa s, uint32_t n, uint32_t off) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = off + i;
+  s.x[j] = p.x[i];
+  s.y[j] = p.y[i];
+  s.z[j] = p.z[i];
+  s.u[j] = p.u[i];
+  s.v[j] = p.v[i];
+  s.w[j] = p.w[i];
+  s.T[j] = p.T[i];
+  s.nlam[j] = p.nlam[i];
+  s.k0[j] = p.k0[i];
+  s.k1[j] = p.k1[i];
+  s.k2[j] = p.k2[i];
+  s.event[j] = p.evt[i];
+  s.nstep[j] = p.nstep[i];
+  s.species[j] = (int32_t)(p.meta[i] & 3u);
+  s.vol[j] = (int32_t)(p.meta[i] >> 2);
 }
 
 }  // namespace ems
@@ -975,19 +1225,37 @@ namespace ems {
 
 static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
-hipError_t launch_step(const Params& P, const Pool& in, const Pool& out, uint32_t n_in,
-                       uint32_t n_step, bool mixed, ems_step_record* rec, hipStream_t s) {
-  if (n_in == 0) return hipSuccess;
-  const dim3 g(blocks_for(n_in, kBlock)), b(kBlock);
-  if (mixed) hipLaunchKernelGGL(k_step<float>, g, b, 0, s, P, in, out, n_in, n_step, rec);
-  else hipLaunchKernelGGL(k_step<double>, g, b, 0, s, P, in, out, n_in, n_step, rec);
+hipError_t launch_iteration(const Params& P, const Pool& inG, const Pool& inC, uint32_t nG,
+                            uint32_t kG, uint32_t nC, uint32_t kC, const Pool& outG,
+                            const Pool& outC, const IQueue& Q, bool mixed, ems_step_record* rec,
+                            hipStream_t s) {
+  const uint32_t nbG = blocks_for(nG, kBlock), nbC = blocks_for(nC, kBlock);
+  if (nbG + nbC == 0) return hipSuccess;
+  const dim3 b(kBlock);
+  if (mixed)
+    hipLaunchKernelGGL(k_transport<float>, dim3(nbG + nbC), b, 0, s, P, inG, inC, nG, kG, nC, kC,
+                       nbG, outG, outC, Q, rec);
+  else
+    hipLaunchKernelGGL(k_transport<double>, dim3(nbG + nbC), b, 0, s, P, inG, inC, nG, kG, nC,
+                       kC, nbG, outG, outC, Q, rec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // at most kG + kC queued tracks; each queue adds at most one partial block
+  const uint32_t nbI = blocks_for((uint64_t)kG + kC, kBlock) + kNumQueues;
+  if (mixed) hipLaunchKernelGGL(k_interact<float>, dim3(nbI), b, 0, s, P, Q, outG, outC, rec);
+  else hipLaunchKernelGGL(k_interact<double>, dim3(nbI), b, 0, s, P, Q, outG, outC, rec);
   return hipGetLastError();
 }
 
-hipError_t launch_admit(const Params& P, const Queue& q, const Pool& pool, uint32_t head,
-                        uint32_t m, uint32_t n0, hipStream_t s) {
+hipError_t launch_iter_begin(uint32_t* counters, uint32_t nG, uint32_t nC, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(64), 0, s, counters, nG, nC);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit(const Params& P, const Queue& q, const Pool& poolG, const Pool& poolC,
+                        uint32_t head, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, q, pool, head, m, n0);
+  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, q, poolG, poolC, head, m);
   return hipGetLastError();
 }
 
@@ -1027,15 +1295,17 @@ hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pool_load(const Pool& p, const ems_track_soa& src, uint32_t n, hipStream_t s) {
+hipError_t launch_pool_load(const Params& P, const Pool& pg, const Pool& pc,
+                            const ems_track_soa& src, uint32_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_load, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, src, n);
+  hipLaunchKernelGGL(k_pool_load, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, pg, pc, src, n);
   return hipGetLastError();
 }
 
-hipError_t launch_pool_dump(const Pool& p, const ems_track_soa& dst, uint32_t n, hipStream_t s) {
+hipError_t launch_pool_dump(const Pool& p, const ems_track_soa& dst, uint32_t n, uint32_t off,
+                            hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_dump, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, dst, n);
+  hipLaunchKernelGGL(k_pool_dump, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, dst, n, off);
   return hipGetLastError();
 }
 
