@@ -19,7 +19,7 @@ constexpr int kLedger = 4;            // escaped (fixed point), killed (fixed po
 constexpr uint32_t kVolOut = 0x3FFFFFFFu;  // meta volume of a primary that starts outside
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
 
 // Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.  Photons and
 // charged tracks live in separate pools so that a wavefront steps one species
@@ -44,11 +44,19 @@ struct IQueue {
   uint32_t capacity;  // per queue; queue q occupies [q * capacity, (q + 1) * capacity)
 };
 
-// Device counters of one iteration.
-enum CounterId {
-  kCOutG = 0, kCOutC = 1, kCDone = 2, kCQueue = 3,  // kCQueue + q: queue sizes
-  kCAdmitG = 11, kCAdmitC = 12, kNumCounters = 16
+// Device counters of one iteration.  Each counter line is 256 bytes apart so that
+// concurrent atomics on different counters meet different cache lines and memory
+// channels; two 32-bit counters share one 64-bit word (low, high) and are
+// advanced together by one 64-bit atomic.
+enum CounterLine {
+  kLOut = 0,      // output pools: photons (low), charged (high)
+  kLQueue = 1,    // lines 1..4: queue sizes (2i low, 2i+1 high)
+  kLDone = 5,     // finished-event list length (low)
+  kLAdmit = 6,    // admission cursors: photons (low), charged (high)
+  kLPosSteps = 7, // positron track-steps of the iteration
+  kNumLines = 8
 };
+constexpr int kLineWords = 32;  // 64-bit words per line
 
 struct MatParams {
   double Tc, kc;      // production thresholds (delta rays, brems photons)
@@ -83,8 +91,7 @@ struct Params {
   int* alive;                    // [slot] tracks alive or queued
   const double* scale;           // [slot] fixed-point scale 2^s
   uint32_t* done;                // [slot] list of finished slots (append)
-  uint32_t* counters;            // CounterId
-  unsigned long long* steps;     // [3] track-steps by species
+  unsigned long long* ctr;       // kNumLines x kLineWords iteration counters
   unsigned long long* esc_hist;  // [3][kGrid]
 };
 

@@ -89,9 +89,10 @@ struct ems_ctx {
   uint32_t* stage_slot = nullptr;
   uint32_t* stage_id = nullptr;
   double* stage_out = nullptr;
-  uint32_t* counters = nullptr;
+  unsigned long long* ctr = nullptr;
   // pinned host mirror of the counters and done list
-  uint32_t* h_counters = nullptr;
+  unsigned long long* h_ctr = nullptr;
+  uint64_t run_steps[3] = {0, 0, 0};  // track-steps by species since init_geometry
   uint32_t* h_done = nullptr;
   // event slots
   std::vector<uint32_t> free_slots;
@@ -160,8 +161,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   double* scale = c.take<double>(E);
   double* e_in = c.take<double>(E);
   uint32_t* done = c.take<uint32_t>(E);
-  uint32_t* counters = c.take<uint32_t>(kNumCounters);
-  unsigned long long* steps = c.take<unsigned long long>(4);
+  unsigned long long* ctr = c.take<unsigned long long>(kNumLines * kLineWords);
   unsigned long long* esc = c.take<unsigned long long>(3 * kGrid);
   Queue q;
   q.species = c.take<int32_t>(Qc);
@@ -199,12 +199,11 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->P.alive = alive;
   x->P.scale = scale;
   x->P.done = done;
-  x->P.counters = counters;
-  x->P.steps = steps;
+  x->P.ctr = ctr;
   x->P.esc_hist = esc;
   x->scale = scale;
   x->e_in = e_in;
-  x->counters = counters;
+  x->ctr = ctr;
   x->q = q;
   x->stage_off = so;
   x->stage_slot = ss;
@@ -265,12 +264,13 @@ ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, em
   carve(c, *cfg, x);
   x->P.seed = cfg->seed;
   x->P.max_events = cfg->max_events;
-  hipError_t e = hipHostMalloc((void**)&x->h_counters, kNumCounters * sizeof(uint32_t), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&x->h_ctr, kNumLines * kLineWords * sizeof(unsigned long long),
+                               hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
                       hipHostMallocDefault);
   if (e != hipSuccess) {
-    if (x->h_counters) (void)hipHostFree(x->h_counters);
+    if (x->h_ctr) (void)hipHostFree(x->h_ctr);
     delete x;
     return fail(EMS_E_HIP, std::string("ems_create: pinned host buffer: ") + hipGetErrorString(e));
   }
@@ -287,7 +287,7 @@ ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, em
 
 void ems_destroy(ems_ctx* x) {
   if (!x) return;
-  if (x->h_counters) (void)hipHostFree(x->h_counters);
+  if (x->h_ctr) (void)hipHostFree(x->h_ctr);
   if (x->h_done) (void)hipHostFree(x->h_done);
   if (x->ev0) (void)hipEventDestroy(x->ev0);
   if (x->ev1) (void)hipEventDestroy(x->ev1);
@@ -370,8 +370,8 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
   P.hz = g->half_z;
   P.bz = g->bz;
   P.ftol = g->field_tol;
-  HIP_OK(launch_zero_u32(x->counters, kNumCounters, s));
-  HIP_OK(launch_zero_u64(P.steps, 4, s));
+  HIP_OK(launch_zero_u64(x->ctr, kNumLines * kLineWords, s));
+  x->run_steps[0] = x->run_steps[1] = x->run_steps[2] = 0;
   HIP_OK(launch_zero_u64(P.esc_hist, 3 * kGrid, s));
   HIP_OK(hipStreamSynchronize(s));
   reset_events(x);
@@ -453,9 +453,10 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
   const uint32_t n_active = x->nG + x->nC;
   while (!x->pending.empty()) {
     const EventInfo& ev = x->pending.front();
+    // an empty pool always takes the next event, so admission cannot stall
     const bool first = n_active + m == 0;
     if (!first && n_active + m + ev.n_prim > room) break;
-    if (budget > 0.0 && x->e_flight > 0.0 && x->e_flight + ev.e_in > budget) break;
+    if (!first && budget > 0.0 && x->e_flight > 0.0 && x->e_flight + ev.e_in > budget) break;
     m += ev.n_prim;
     mg += ev.n_gamma;
     x->e_flight += ev.e_in;
@@ -475,14 +476,18 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
 // One step iteration (admission, transport, interactions) and its readback.
 ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* stepped,
                    uint64_t* deferred, bool admit_first) {
-  HIP_OK(launch_iter_begin(x->counters, x->nG, x->nC, s));
+  HIP_OK(launch_iter_begin(x->ctr, x->nG, x->nC, s));
   if (admit_first) {
     uint32_t m = 0;
     const ems_status st = admit(x, s, &m);
     if (st != EMS_OK) return st;
   }
   const uint32_t nG = x->nG, nC = x->nC, n = nG + nC;
-  if (n == 0) return EMS_OK;
+  if (n == 0) {
+    if (admit_first && !x->pending.empty())
+      return fail(EMS_E_INTERNAL, "transport_events: queued events could not be admitted");
+    return EMS_OK;
+  }
   const uint32_t cap = x->cfg.pool_capacity;
   // every stepped track leaves at most three tracks, so n + 2k <= cap bounds both pools
   const uint32_t k = std::min<uint64_t>(n, (uint64_t)(cap - n) / 2);
@@ -493,16 +498,24 @@ ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* st
                           x->pool[0][1 - x->cur], x->pool[1][1 - x->cur], x->iq,
                           x->cfg.precision == EMS_MIXED, rec, s));
   if (x->ev1) HIP_OK(hipEventRecord(x->ev1, s));
-  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, kNumCounters * sizeof(uint32_t),
+  HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  const uint32_t outG = x->h_counters[kCOutG], outC = x->h_counters[kCOutC];
-  const uint32_t n_done = std::min(x->h_counters[kCDone], x->cfg.max_events);
+  const unsigned long long* L = x->h_ctr;
+  const uint32_t outG = (uint32_t)L[kLOut * kLineWords], outC = (uint32_t)(L[kLOut * kLineWords] >> 32);
+  const uint32_t n_done = std::min((uint32_t)L[kLDone * kLineWords], x->cfg.max_events);
+  const uint64_t pos_steps = L[kLPosSteps * kLineWords];
+  x->run_steps[EMS_GAMMA] += kG;
+  x->run_steps[EMS_POSITRON] += pos_steps;
+  x->run_steps[EMS_ELECTRON] += kC - pos_steps;
   x->stats.launches += 1;
   x->stats.tracks_in += n;
   x->stats.tracks_out += (uint64_t)outG + outC;
   uint64_t queued = 0;
-  for (int q = 0; q < kNumQueues; ++q) queued += x->h_counters[kCQueue + q];
+  for (int q = 0; q < kNumQueues; ++q) {
+    const unsigned long long v = L[(kLQueue + q / 2) * kLineWords];
+    queued += (q & 1) ? (v >> 32) : (v & 0xFFFFFFFFull);
+  }
   x->stats.queued += queued;
   if (x->ev0) {
     float ms = 0.f;
@@ -613,12 +626,11 @@ ems_status ems_run_counters(ems_ctx* x, uint64_t* steps, uint64_t* esc_hist, voi
   if (!x || !steps) return fail(EMS_E_ARG, "ems_run_counters: null argument");
   if (!x->geometry) return fail(EMS_E_STATE, "ems_run_counters: no geometry");
   hipStream_t s = (hipStream_t)stream;
-  unsigned long long st[4];
-  HIP_OK(hipMemcpyAsync(st, x->P.steps, sizeof(st), hipMemcpyDeviceToHost, s));
-  if (esc_hist)
+  if (esc_hist) {
     HIP_OK(hipMemcpyAsync(esc_hist, x->P.esc_hist, 3 * kGrid * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  for (int i = 0; i < 3; ++i) steps[i] = st[i];
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  for (int i = 0; i < 3; ++i) steps[i] = x->run_steps[i];
   return EMS_OK;
 }
 
@@ -639,13 +651,13 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   // every slot of this context is reset: step_once discards any events in flight
   reset_events(x);
   HIP_OK(launch_slots_reset(x->P, s));
-  HIP_OK(launch_iter_begin(x->counters, 0, 0, s));
+  HIP_OK(launch_iter_begin(x->ctr, 0, 0, s));
   HIP_OK(launch_pool_load(x->P, x->pool[0][0], x->pool[1][0], *in, n, s));
-  HIP_OK(hipMemcpyAsync(x->h_counters, x->counters, kNumCounters * sizeof(uint32_t),
+  HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  x->nG = x->h_counters[kCAdmitG];
-  x->nC = x->h_counters[kCAdmitC];
+  x->nG = (uint32_t)x->h_ctr[kLAdmit * kLineWords];
+  x->nC = (uint32_t)(x->h_ctr[kLAdmit * kLineWords] >> 32);
   uint64_t stepped = 0, deferred = 0;
   ems_status st = iterate(x, s, rec, &stepped, &deferred, false);
   if (st != EMS_OK) return st;

@@ -15,7 +15,7 @@ hipError_t launch_iteration(const Params& P, const Pool& inG, const Pool& inC, u
                             uint32_t kG, uint32_t nC, uint32_t kC, const Pool& outG,
                             const Pool& outC, const IQueue& Q, bool mixed, ems_step_record* rec,
                             hipStream_t s);
-hipError_t launch_iter_begin(uint32_t* counters, uint32_t nG, uint32_t nC, hipStream_t s);
+hipError_t launch_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC, hipStream_t s);
 hipError_t launch_admit(const Params& P, const Queue& q, const Pool& poolG, const Pool& poolC,
                         uint32_t head, uint32_t m, hipStream_t s);
 hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, const uint32_t* slots,

@@ -729,6 +729,19 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, int lane) {
   return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
+__device__ __forceinline__ unsigned long long* ctr_line(const Params& P, int l) {
+  return P.ctr + (size_t)l * kLineWords;
+}
+
+__device__ __forceinline__ uint32_t lo32(unsigned long long v) { return (uint32_t)(v & 0xFFFFFFFFull); }
+__device__ __forceinline__ uint32_t hi32(unsigned long long v) { return (uint32_t)(v >> 32); }
+
+// size of interaction queue q this iteration
+__device__ __forceinline__ uint32_t queue_size(const Params& P, int q) {
+  const unsigned long long v = *ctr_line(P, kLQueue + (q >> 1));
+  return (q & 1) ? hi32(v) : lo32(v);
+}
+
 __device__ __forceinline__ void write_track(const Pool& p, uint32_t j, int sp, int vol, double x,
                                             double y, double z, double u, double v, double w,
                                             double T, double nlam, uint32_t k0, uint32_t k1,
@@ -768,7 +781,7 @@ __device__ __forceinline__ void count_done(const Params& P, uint32_t e, int delt
   if (delta == 0) return;
   const int old = atomicAdd(&P.alive[e], delta);
   if (old + delta == 0) {
-    const uint32_t k = atomicAdd(&P.counters[kCDone], 1u);
+    const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
     if (k < P.max_events) P.done[k] = e;
   }
 }
@@ -835,8 +848,8 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
   }
 
   // ---- block-level reservation: stream 0 survivors (output pool of this class),
-  // 1..8 process queues, 9..11 track-steps by species; one atomic per block and stream
-  constexpr int kW = kBlock / 64, kS = 12;
+  // 1..8 process queues, 9 positron track-steps; one 64-bit atomic per counter line
+  constexpr int kW = kBlock / 64, kS = 10;
   __shared__ uint32_t sh_cnt[kW][kS];
   __shared__ uint32_t sh_base[kS];
   const int wave = threadIdx.x >> 6;
@@ -844,31 +857,38 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
   uint64_t mq[kNumQueues];
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) mq[q] = __ballot(o.dest == q);
-  uint64_t mst[3];
-#pragma unroll
-  for (int sp = 0; sp < 3; ++sp) mst[sp] = __ballot(stepped && t.sp == sp);
+  const uint64_t mpos = __ballot(stepped && t.sp == EMS_POSITRON);
   if (lane == 0) {
     sh_cnt[wave][0] = (uint32_t)__popcll(mS);
 #pragma unroll
     for (int q = 0; q < kNumQueues; ++q) sh_cnt[wave][1 + q] = (uint32_t)__popcll(mq[q]);
-#pragma unroll
-    for (int sp = 0; sp < 3; ++sp) sh_cnt[wave][9 + sp] = (uint32_t)__popcll(mst[sp]);
+    sh_cnt[wave][9] = (uint32_t)__popcll(mpos);
   }
   __syncthreads();
-  if (threadIdx.x < kS) {
-    const int st = threadIdx.x;
-    uint32_t tot = 0;
+  if (threadIdx.x < 6) {
+    const int l = threadIdx.x;  // counter line handled by this thread
+    auto tot = [&](int st) {
+      uint32_t t2 = 0;
 #pragma unroll
-    for (int w2 = 0; w2 < kW; ++w2) tot += sh_cnt[w2][st];
-    uint32_t b0 = 0;
-    if (st == 0) {
-      if (tot) b0 = atomicAdd(&P.counters[cblk ? kCOutC : kCOutG], tot);
-    } else if (st < 9) {
-      if (tot) b0 = atomicAdd(&P.counters[kCQueue + st - 1], tot);
-    } else if (tot) {
-      atomicAdd(&P.steps[st - 9], (unsigned long long)tot);
+      for (int w2 = 0; w2 < kW; ++w2) t2 += sh_cnt[w2][st];
+      return t2;
+    };
+    if (l == 0) {
+      const uint32_t a = tot(0);
+      unsigned long long old = 0;
+      if (a) old = atomicAdd(ctr_line(P, kLOut), cblk ? ((unsigned long long)a << 32) : a);
+      sh_base[0] = cblk ? hi32(old) : lo32(old);
+    } else if (l <= 4) {
+      const int s0 = 1 + 2 * (l - 1);
+      const uint32_t a = tot(s0), b = tot(s0 + 1);
+      unsigned long long old = 0;
+      if (a | b) old = atomicAdd(ctr_line(P, kLQueue + l - 1), ((unsigned long long)b << 32) | a);
+      sh_base[s0] = lo32(old);
+      sh_base[s0 + 1] = hi32(old);
+    } else {
+      const uint32_t a = tot(9);
+      if (a) atomicAdd(ctr_line(P, kLPosSteps), (unsigned long long)a);
     }
-    sh_base[st] = b0;
   }
   __syncthreads();
   if (o.dest == -1) {
@@ -945,7 +965,7 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
   uint32_t start = 0, qsel = kNumQueues, cnt = 0;
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) {
-    const uint32_t c = P.counters[kCQueue + q];
+    const uint32_t c = queue_size(P, q);
     const uint32_t nb = (c + kBlock - 1) / kBlock;
     if (qsel == kNumQueues && blockIdx.x < start + nb) {
       qsel = q;
@@ -1007,11 +1027,17 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
     sh_cnt[wave][1] = nc0 + nc1 + nc2 + nc3;
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
-    uint32_t tot = 0;
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
 #pragma unroll
-    for (int w2 = 0; w2 < kW; ++w2) tot += sh_cnt[w2][threadIdx.x];
-    sh_base[threadIdx.x] = tot ? atomicAdd(&P.counters[threadIdx.x == 0 ? kCOutG : kCOutC], tot) : 0u;
+    for (int w2 = 0; w2 < kW; ++w2) {
+      a += sh_cnt[w2][0];
+      b += sh_cnt[w2][1];
+    }
+    unsigned long long old = 0;
+    if (a | b) old = atomicAdd(ctr_line(P, kLOut), ((unsigned long long)b << 32) | a);
+    sh_base[0] = lo32(old);
+    sh_base[1] = hi32(old);
   }
   __syncthreads();
   uint32_t bg = sh_base[0], bc = sh_base[1];
@@ -1064,9 +1090,10 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
 
 // Start of an iteration: clear the iteration counters and set the admission
 // cursors to the current pool sizes.
-__global__ void k_iter_begin(uint32_t* counters, uint32_t nG, uint32_t nC) {
+__global__ void k_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC) {
   const int j = threadIdx.x;
-  if (j < kNumCounters) counters[j] = j == kCAdmitG ? nG : (j == kCAdmitC ? nC : 0u);
+  if (j < kNumLines * kLineWords)
+    ctr[j] = j == kLAdmit * kLineWords ? (((unsigned long long)nC << 32) | nG) : 0ull;
 }
 
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
@@ -1079,11 +1106,12 @@ __global__ void k_admit(Params P, Queue q, Pool poolG, Pool poolC, uint32_t head
   const int sp = valid ? q.species[r] : 0;
   const bool g = valid && sp == EMS_GAMMA, c = valid && sp != EMS_GAMMA;
   const uint64_t mg = __ballot(g), mc = __ballot(c);
-  uint32_t bg = 0, bc = 0;
-  if (lane == 0 && mg) bg = atomicAdd(&P.counters[kCAdmitG], (uint32_t)__popcll(mg));
-  if (lane == 0 && mc) bc = atomicAdd(&P.counters[kCAdmitC], (uint32_t)__popcll(mc));
-  bg = __shfl(bg, 0);
-  bc = __shfl(bc, 0);
+  unsigned long long old = 0;
+  if (lane == 0 && (mg | mc))
+    old = atomicAdd(ctr_line(P, kLAdmit),
+                    ((unsigned long long)__popcll(mc) << 32) | (unsigned long long)__popcll(mg));
+  old = __shfl(old, 0);
+  const uint32_t bg = lo32(old), bc = hi32(old);
   if (!valid) return;
   const double x = q.x[r], y = q.y[r], z = q.z[r], u = q.u[r], v = q.v[r], w = q.w[r];
   uint32_t a, b, cc, d;
@@ -1183,11 +1211,12 @@ __global__ void k_pool_load(Params P, Pool pg, Pool pc, ems_track_soa s, uint32_
   const int sp = valid ? s.species[j] : 0;
   const bool g = valid && sp == EMS_GAMMA, c = valid && sp != EMS_GAMMA;
   const uint64_t mg = __ballot(g), mc = __ballot(c);
-  uint32_t bg = 0, bc = 0;
-  if (lane == 0 && mg) bg = atomicAdd(&P.counters[kCAdmitG], (uint32_t)__popcll(mg));
-  if (lane == 0 && mc) bc = atomicAdd(&P.counters[kCAdmitC], (uint32_t)__popcll(mc));
-  bg = __shfl(bg, 0);
-  bc = __shfl(bc, 0);
+  unsigned long long old = 0;
+  if (lane == 0 && (mg | mc))
+    old = atomicAdd(ctr_line(P, kLAdmit),
+                    ((unsigned long long)__popcll(mc) << 32) | (unsigned long long)__popcll(mg));
+  old = __shfl(old, 0);
+  const uint32_t bg = lo32(old), bc = hi32(old);
   if (!valid) return;
   const Pool& p = g ? pg : pc;
   const uint32_t k = g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane);
@@ -1247,8 +1276,8 @@ hipError_t launch_iteration(const Params& P, const Pool& inG, const Pool& inC, u
   return hipGetLastError();
 }
 
-hipError_t launch_iter_begin(uint32_t* counters, uint32_t nG, uint32_t nC, hipStream_t s) {
-  hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(64), 0, s, counters, nG, nC);
+hipError_t launch_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(kNumLines * kLineWords), 0, s, ctr, nG, nC);
   return hipGetLastError();
 }
 
