@@ -103,6 +103,9 @@ def lib() -> C.CDLL:
             "or_locate": (i, [C.c_void_p, d, d, d, d, d, d]),
             "or_distance": (d, [C.c_void_p, i, P(d), P(d), P(i)]),
             "or_step": (i, [C.c_void_p, u32, P(Track), P(StepResult)]),
+            "or_field_kappa": (d, [d, d, d]),
+            "or_rk4": (None, [d, d, P(d), P(d), P(d), P(d)]),
+            "or_field_move": (i, [C.c_void_p, i, d, d, i, P(d), P(d), P(d), P(i)]),
             "or_run_batch": (i, [C.c_void_p, u32, i, P(u32), P(C.c_int64), P(i), P(d), P(d),
                                  P(d), P(d), P(d), P(C.c_int64), P(C.c_int64), C.c_void_p]),
         }
@@ -230,6 +233,15 @@ class World:
 
     def locate(self, pos, d):
         return lib().or_locate(self.h, *[float(x) for x in pos], *[float(x) for x in d])
+
+    def field_move(self, vol, kappa, s_max, vacuum, pos, d):
+        """Curved move of a charged track; returns (status, path, pos, dir, next)."""
+        p = (C.c_double * 3)(*pos)
+        q = (C.c_double * 3)(*d)
+        sl = C.c_double()
+        nx = C.c_int()
+        st = lib().or_field_move(self.h, vol, kappa, s_max, vacuum, p, q, C.byref(sl), C.byref(nx))
+        return st, sl.value, list(p), list(q), nx.value
 
     def distance(self, vol, pos, d):
         p = (C.c_double * 3)(*pos)

@@ -38,7 +38,7 @@ enum { OR_GAMMA = 0, OR_ELECTRON = 1, OR_POSITRON = 2 };
 enum { OR_NGRID = 200, OR_NQ = 4, OR_MAXMAT = 8 };
 enum { OR_GEOM_SLABS = 0, OR_GEOM_CYLINDERS = 1 };
 enum { OR_OUTSIDE = -1 };
-enum { OR_LIM_GEO = 0, OR_LIM_PHYS = 1, OR_LIM_CONT = 2 };
+enum { OR_LIM_GEO = 0, OR_LIM_PHYS = 1, OR_LIM_CONT = 2, OR_LIM_LOOPER = 3 };
 
 typedef struct {
   double Z, A, density, mean_excitation; /* mean_excitation in MeV; density 0 = vacuum */
@@ -149,6 +149,14 @@ double or_material_X0(const or_world* w, int mat);
 int or_locate(const or_world* w, double x, double y, double z, double u, double v, double wz);
 double or_distance(const or_world* w, int vol, const double pos[3], const double dir[3],
                    int* next);
+
+/* Charged tracks in the uniform field B_z: curvature, one RK4 step, and the curved
+ * move of a step (returns 0 at s_max, 1 at a boundary, 2 for a looper). */
+double or_field_kappa(double q, double bz, double p);
+void or_rk4(double kappa, double h, const double r[3], const double d[3], double ro[3],
+            double dout[3]);
+int or_field_move(const or_world* w, int vol, double kappa, double s_max, int vacuum, double r[3],
+                  double d[3], double* s_out, int* next);
 
 int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result* res);
 

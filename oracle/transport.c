@@ -484,25 +484,35 @@ int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result
 
   double pos[3] = {t.x, t.y, t.z}, dir[3] = {t.u, t.v, t.w};
   int next = OR_OUTSIDE;
-  const double s_geo = or_distance(w, t.vol, pos, dir, &next);
-
   int lim;
   double s;
-  if (s_geo <= s_phys && s_geo <= s_cont) {
-    lim = OR_LIM_GEO;
-    s = s_geo;
-  } else if (s_phys <= s_cont) {
-    lim = OR_LIM_PHYS;
-    s = s_phys;
+  if (charged && g->bz != 0.0) {
+    /* curved path up to the physics limit; the boundary, if met first, wins */
+    const double p = sqrt(t.T * (t.T + 2.0 * OR_ME));
+    const double kappa = or_field_kappa(sp == OR_ELECTRON ? -1.0 : 1.0, g->bz, p);
+    const int res = or_field_move(w, t.vol, kappa, fmin(s_phys, s_cont), !in_matter, pos, dir, &s,
+                                  &next);
+    if (res == 1) lim = OR_LIM_GEO;
+    else if (res == 2) lim = OR_LIM_LOOPER;
+    else lim = s_phys <= s_cont ? OR_LIM_PHYS : OR_LIM_CONT;
   } else {
-    lim = OR_LIM_CONT;
-    s = s_cont;
+    const double s_geo = or_distance(w, t.vol, pos, dir, &next);
+    if (s_geo <= s_phys && s_geo <= s_cont) {
+      lim = OR_LIM_GEO;
+      s = s_geo;
+    } else if (s_phys <= s_cont) {
+      lim = OR_LIM_PHYS;
+      s = s_phys;
+    } else {
+      lim = OR_LIM_CONT;
+      s = s_cont;
+    }
+    pos[0] += s * dir[0];
+    pos[1] += s * dir[1];
+    pos[2] += s * dir[2];
   }
   r->limiter = lim;
   r->step_len = s;
-  pos[0] += s * dir[0];
-  pos[1] += s * dir[1];
-  pos[2] += s * dir[2];
 
   double T1 = t.T, lnT1 = lnT;
   int stopped = 0;
@@ -529,6 +539,9 @@ int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result
   post.y = pos[1];
   post.z = pos[2];
   post.T = T1;
+  post.u = dir[0];
+  post.v = dir[1];
+  post.w = dir[2];
   emitter em = {r, w, seed, &post};
   /* emit() keys children by the parent's pre-increment step */
   post.nstep = t.nstep;
@@ -541,6 +554,9 @@ int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result
     r->dep += T1;
     alive = 0;
     if (sp == OR_POSITRON) annihilate_at_rest(&em, t.key);
+  } else if (lim == OR_LIM_LOOPER) {
+    r->killed += T1;
+    alive = 0;
   } else if (lim == OR_LIM_GEO) {
     if (next == OR_OUTSIDE) {
       r->esc += T1;
