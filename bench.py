@@ -70,6 +70,70 @@ def cpu_baseline(n_events, energy, seed, budget_s=12.0):
                        f"{wall:.1f} s wall, {len(jobs)} processes)")
 
 
+def run_transport(ems, wl, n_events, args, precision, log_name):
+    """Transport the whole batch args.warmup + args.steps times; returns the timed totals."""
+    import torch
+    n_steps = args.warmup + args.steps
+    ctx = ems.Context(pool_capacity=args.pool, max_events=n_events * n_steps,
+                      max_bins=wl.geometry.n_bins, queue_capacity=n_events, seed=wl.seed,
+                      precision=precision, energy_budget=args.budget, time_steps=True)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    batches = []
+    for j in range(n_steps):
+        ev = wl.events.subset(np.arange(n_events))
+        ev.event_ids = (np.arange(n_events) + j * n_events).astype(np.uint32)
+        batches.append(ems.DeviceEvents(ev))
+    torch.cuda.synchronize()
+    total_steps, iters, peak = 0, 0, 0
+    t0 = time.perf_counter()
+    for j in range(n_steps):
+        timed = j >= args.warmup
+        if timed and j == args.warmup:
+            ctx.step_stats(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        ts = time.perf_counter()
+        pr = ctx.transport(batches[j], -1)
+        torch.cuda.synchronize()
+        log(f"{log_name} step {j} ({'timed' if timed else 'warmup'}): {pr.track_steps} track-steps "
+            f"in {time.perf_counter() - ts:.3f} s, {pr.iterations} iterations, peak pool "
+            f"{pr.peak_alive}, deferred {pr.deferred}")
+        if timed:
+            total_steps += pr.track_steps
+            iters += pr.iterations
+            peak = max(peak, pr.peak_alive)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    st = ctx.step_stats()
+    ids = np.concatenate([b.ids for b in batches[args.warmup:]])
+    dep, led, status = ctx.read(ids)
+    assert (status == 0).all()
+    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
+    layers = dep.reshape(len(ids), -1).sum(0)
+    ctx.close()
+    return dict(steps=total_steps, t=t_run, iters=iters, peak=peak, stats=st, layers=layers,
+                ledger_max=float(np.abs(bal / led[:, 0]).max()))
+
+
+def run_serving(ems, args, precision):
+    from paper_2203_09467_amd.serve import serve
+    import workloads as W
+    wl = W.serving(n_events=args.serve_events, rate_hz=args.serve_rate)
+    ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
+                      max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
+                      seed=wl.seed, precision=precision, energy_budget=args.budget,
+                      iterations_per_sync=4)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    res = serve(ctx, wl.events, iterations=4, time_limit=300.0)
+    ctx.close()
+    e_mean = float(wl.events.energy.sum() / wl.events.n_events)
+    return {"p50_ms": res["p50"] * 1e3, "p99_ms": res["p99"] * 1e3,
+            "events": wl.events.n_events, "offered_rate_hz": args.serve_rate,
+            "mean_event_energy_GeV": e_mean / 1000.0,
+            "track_steps_per_s": res["track_steps"] / res["wall"], "wall_s": res["wall"],
+            "peak_events_in_flight": res["peak_events"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +145,10 @@ def main():
     ap.add_argument("--pool", type=int, default=1 << 24)
     ap.add_argument("--budget", type=float, default=2.5e7, help="energy in flight, MeV")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-events", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times, "
                          "to scale HBM byte counters")
@@ -100,59 +168,15 @@ def main():
                           "launches": 3}))
         return
 
-    import torch
-
     import paper_2203_09467_amd as ems
     import workloads as W
 
     seed = 2
     wl = W.calorimeter(args.events, energy=args.energy, seed=seed)
-    n_steps = args.warmup + args.steps
     prec = ems.EMS_FP64 if args.precision == "fp64" else ems.EMS_MIXED
-    ctx = ems.Context(pool_capacity=args.pool, max_events=args.events * n_steps,
-                      max_bins=wl.geometry.n_bins, queue_capacity=args.events, seed=seed,
-                      precision=prec, energy_budget=args.budget, time_steps=True)
-    ctx.setup(wl.materials, wl.options, wl.geometry)
-    batches = []
-    for j in range(n_steps):
-        ev = wl.events.subset(np.arange(args.events))
-        ev.event_ids = (np.arange(args.events) + j * args.events).astype(np.uint32)
-        batches.append(ems.DeviceEvents(ev))
-    torch.cuda.synchronize()
-
-    total_steps = 0
-    t_run = 0.0
-    iters = 0
-    peak = 0
-    for j in range(n_steps):
-        timed = j >= args.warmup
-        if timed and j == args.warmup:
-            ctx.step_stats(reset=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        ts = time.perf_counter()
-        pr = ctx.transport(batches[j], -1)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - ts
-        log(f"step {j} ({'timed' if timed else 'warmup'}): {pr.track_steps} track-steps in "
-            f"{dt:.3f} s, {pr.iterations} iterations, peak pool {pr.peak_alive}, "
-            f"deferred {pr.deferred}")
-        if timed:
-            total_steps += pr.track_steps
-            iters += pr.iterations
-            peak = max(peak, pr.peak_alive)
-    torch.cuda.synchronize()
-    t_run = time.perf_counter() - t0
-    st = ctx.step_stats()
-
-    # correctness of what was timed: every event conserves energy
-    ids = np.concatenate([b.ids for b in batches[args.warmup:]])
-    dep, led, status = ctx.read(ids)
-    assert (status == 0).all()
-    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
-    ledger_max = float(np.abs(bal / led[:, 0]).max())
-
-    value = total_steps / t_run
+    r = run_transport(ems, wl, args.events, args, prec, args.precision)
+    value = r["steps"] / r["t"]
+    st = r["stats"]
     bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out)
     kernel_s = st.kernel_ms / 1e3
     achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
@@ -163,7 +187,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_run / args.steps * 1e3,
+        "ms_per_step": r["t"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -172,16 +196,30 @@ def main():
         "config": {"workload": f"calorimeter: {args.events} x {args.energy / 1000:g} GeV e- on "
                                "50 x (2 mm Pb + 5 mm LAr), 40x40 cm, 0.7 mm cut, seed 2",
                    "precision": args.precision, "pool_slots": args.pool,
-                   "energy_budget_MeV": args.budget, "iterations": iters,
-                   "peak_tracks_in_flight": peak, "track_steps": total_steps,
-                   "ledger_max_rel_error": ledger_max},
+                   "energy_budget_MeV": args.budget, "iterations": r["iters"],
+                   "peak_tracks_in_flight": r["peak"], "track_steps": r["steps"],
+                   "ledger_max_rel_error": r["ledger_max"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step<double>" if prec == ems.EMS_FP64 else "k_step<float>",
+                     "kernel": "step kernels (k_transport + k_interact)",
                      "launches": st.launches,
-                     "avg_launch_ms": st.kernel_ms / max(st.launches, 1),
-                     "step_kernel_share": kernel_s / t_run},
+                     "avg_iteration_ms": st.kernel_ms / max(st.launches, 1),
+                     "step_kernel_share": kernel_s / r["t"]},
     }
+    if args.precision == "fp64" and not args.no_mixed:
+        m = run_transport(ems, wl, args.events, args, ems.EMS_MIXED, "mixed")
+        big = r["layers"] >= 0.01 * r["layers"].sum()
+        rel = np.abs(m["layers"] - r["layers"])[big] / r["layers"][big]
+        out["mixed"] = {"value": m["steps"] / m["t"], "unit": "track-steps/s",
+                        "speedup_vs_fp64": (m["steps"] / m["t"]) / value,
+                        "max_rel_dev_per_bin_vs_fp64": float(rel.max()),
+                        "ledger_max_rel_error": m["ledger_max"]}
+    if not args.no_serving:
+        log("serving: Poisson arrivals, FP64 then mixed")
+        out["serving"] = {"fp64": run_serving(ems, args, ems.EMS_FP64),
+                          "mixed": run_serving(ems, args, ems.EMS_MIXED),
+                          "workload": "calorimeter geometry; events of U{1..500} primaries "
+                                      "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the oracle on a sample of the batch")
         out["cpu_baseline"] = cpu_baseline(args.events, args.energy, seed)

@@ -64,6 +64,9 @@ typedef struct {
   ems_precision precision;  /* arithmetic of cross sections, interpolation and sampling */
   double energy_budget;     /* MeV of primary energy admitted at once; <= 0: unlimited */
   uint32_t flags;           /* EMS_FLAG_* */
+  uint32_t iterations_per_sync; /* step iterations enqueued per host synchronisation
+                                   (admission and completion bookkeeping happen at
+                                   synchronisations); 0 = 8, at most 32 */
 } ems_config;
 
 /* flags: time every step-kernel launch with HIP events on the launch stream */
@@ -106,8 +109,9 @@ typedef struct {
   const int32_t* tally_bin;  /* host, n_vol bins in [0, n_bins) */
   int32_t n_bins;
   double half_x, half_y, half_z;
-  double bz;                 /* uniform field along z (cylinders only), tesla */
-  double field_tol;          /* cm: RK4 error tolerance per substep */
+  double bz;                 /* uniform field along z, tesla (charged tracks follow RK4
+                                substeps; 0 = straight lines) */
+  double field_tol;          /* cm: RK4 position error and boundary sagitta tolerance */
 } ems_geometry;
 
 /* Primaries of a batch of events; rows of event e are offsets[e] .. offsets[e+1]-1. */
@@ -134,7 +138,8 @@ typedef struct {
 /* Per-track single-step record (diagnostics and parity tests). */
 typedef struct {
   double dep, esc, killed, step_len;
-  int32_t limiter;  /* 0 boundary, 1 discrete interaction, 2 continuous-loss limit */
+  int32_t limiter;  /* 0 boundary, 1 discrete interaction, 2 continuous-loss limit,
+                       3 looper in the field (killed) */
   int32_t process;  /* selected process, -1 none */
   int32_t n_pair, n_annih;
   int32_t n_out;    /* outputs: surviving parent + secondaries */

@@ -48,7 +48,8 @@ class EmsError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("pool_capacity", C.c_uint32), ("max_events", C.c_uint32),
                 ("max_bins", C.c_uint32), ("queue_capacity", C.c_uint32), ("seed", C.c_uint32),
-                ("precision", C.c_int), ("energy_budget", C.c_double), ("flags", C.c_uint32)]
+                ("precision", C.c_int), ("energy_budget", C.c_double), ("flags", C.c_uint32),
+                ("iterations_per_sync", C.c_uint32)]
 
 
 class KernelStats(C.Structure):
@@ -239,16 +240,42 @@ class DeviceEvents:
                           self.species.data_ptr(), self.energy.data_ptr(), self.pos.data_ptr(),
                           self.dir.data_ptr())
 
+    def slice(self, a: int, b: int) -> "EventSlice":
+        """Events [a, b) of this batch, without copying the device arrays."""
+        return EventSlice(self, a, b)
+
+
+class EventSlice:
+    """A contiguous run of events of a DeviceEvents batch (views of its arrays)."""
+
+    def __init__(self, parent: DeviceEvents, a: int, b: int):
+        self.parent = parent
+        self.ids = np.ascontiguousarray(parent.ids[a:b])
+        r0 = int(parent.offsets[a])
+        self.offsets = np.ascontiguousarray(parent.offsets[a:b + 1] - r0)
+        self.r0 = r0
+
+    @property
+    def n_events(self):
+        return int(self.ids.shape[0])
+
+    def c_struct(self) -> EventBatch:
+        p, r0 = self.parent, self.r0
+        self._keep = (self.ids, self.offsets)
+        return EventBatch(self.n_events, _np_ptr(self.ids, C.c_uint32), _np_ptr(self.offsets, C.c_int64),
+                          p.species.data_ptr() + 4 * r0, p.energy.data_ptr() + 8 * r0,
+                          p.pos.data_ptr() + 24 * r0, p.dir.data_ptr() + 24 * r0)
+
 
 class Context:
     """A transport context over a torch-allocated workspace."""
 
     def __init__(self, pool_capacity=1 << 20, max_events=1024, max_bins=128,
                  queue_capacity=1 << 20, seed=1, precision=EMS_FP64, energy_budget=0.0,
-                 time_steps=False, device="cuda"):
+                 time_steps=False, iterations_per_sync=0, device="cuda"):
         import torch
         self.cfg = Config(pool_capacity, max_events, max_bins, queue_capacity, seed, precision,
-                          energy_budget, 1 if time_steps else 0)
+                          energy_budget, 1 if time_steps else 0, iterations_per_sync)
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise EmsError(-1, "ems_workspace_bytes")

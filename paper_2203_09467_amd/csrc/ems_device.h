@@ -23,7 +23,10 @@ constexpr int kBlock = 512;
 
 // Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.  Photons and
 // charged tracks live in separate pools so that a wavefront steps one species
-// class.  src (diagnostics only) is the input index of a single-step call.
+// class, each double-buffered.  A Pool passed to the step kernels is the set of
+// all four buffers: for every field, buffer (class c, parity b) occupies elements
+// [(2c + b) N, (2c + b + 1) N), so a lane picks its destination buffer with one
+// integer offset.  src (diagnostics only) is the input index of a single-step call.
 struct Pool {
   double *x, *y, *z, *u, *v, *w, *T, *nlam;
   uint32_t *k0, *k1, *k2, *evt, *nstep, *meta, *src;
@@ -53,8 +56,14 @@ enum CounterLine {
   kLQueue = 1,    // lines 1..4: queue sizes (2i low, 2i+1 high)
   kLDone = 5,     // finished-event list length (low)
   kLAdmit = 6,    // admission cursors: photons (low), charged (high)
-  kLPosSteps = 7, // positron track-steps of the iteration
-  kNumLines = 8
+  kLPosSteps = 7, // positron track-steps since the interval began
+  kLStats = 8,    // interval statistics, words kS*
+  kNumLines = 9
+};
+// words of the statistics line (sums over the iterations of a sync interval)
+enum StatWord {
+  kSIn = 0, kSStepped = 1, kSStepG = 2, kSStepC = 3, kSOut = 4, kSQueued = 5, kSStall = 6,
+  kSBusy = 7, kSPeak = 8
 };
 constexpr int kLineWords = 32;  // 64-bit words per line
 

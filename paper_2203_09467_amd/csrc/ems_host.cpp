@@ -43,6 +43,7 @@ ems_status fail(ems_status s, const std::string& msg) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxPerSync = 32;
 constexpr uint32_t kMaxVol = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -70,7 +71,8 @@ struct EventInfo {
 struct ems_ctx {
   ems_config cfg{};
   Params P{};
-  Pool pool[2][2]{};  // [class: photon, charged][buffer]
+  Pool set{};         // all four pool buffers (see Pool)
+  Pool pool[2][2]{};  // views [class: photon, charged][buffer]
   IQueue iq{};
   Queue q{};
   int cur = 0;
@@ -105,7 +107,8 @@ struct ems_ctx {
   uint64_t pending_prims = 0;
   double e_flight = 0.0;
   // step-kernel statistics
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev[2 * kMaxPerSync] = {};
+  int per_sync = 8;  // iterations per host synchronisation
   ems_kernel_stats stats{};
 };
 
@@ -113,26 +116,22 @@ namespace {
 
 void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   const size_t N = cfg.pool_capacity, E = cfg.max_events, B = cfg.max_bins, Qc = cfg.queue_capacity;
-  Pool pools[2][2];
-  for (int cl = 0; cl < 2; ++cl)
-    for (int b = 0; b < 2; ++b) {
-      Pool& p = pools[cl][b];
-      p.x = c.take<double>(N);
-      p.y = c.take<double>(N);
-      p.z = c.take<double>(N);
-      p.u = c.take<double>(N);
-      p.v = c.take<double>(N);
-      p.w = c.take<double>(N);
-      p.T = c.take<double>(N);
-      p.nlam = c.take<double>(N);
-      p.k0 = c.take<uint32_t>(N);
-      p.k1 = c.take<uint32_t>(N);
-      p.k2 = c.take<uint32_t>(N);
-      p.evt = c.take<uint32_t>(N);
-      p.nstep = c.take<uint32_t>(N);
-      p.meta = c.take<uint32_t>(N);
-      p.src = c.take<uint32_t>(N);
-    }
+  Pool set;  // four buffers per field: (photon, charged) x (parity 0, 1)
+  set.x = c.take<double>(4 * N);
+  set.y = c.take<double>(4 * N);
+  set.z = c.take<double>(4 * N);
+  set.u = c.take<double>(4 * N);
+  set.v = c.take<double>(4 * N);
+  set.w = c.take<double>(4 * N);
+  set.T = c.take<double>(4 * N);
+  set.nlam = c.take<double>(4 * N);
+  set.k0 = c.take<uint32_t>(4 * N);
+  set.k1 = c.take<uint32_t>(4 * N);
+  set.k2 = c.take<uint32_t>(4 * N);
+  set.evt = c.take<uint32_t>(4 * N);
+  set.nstep = c.take<uint32_t>(4 * N);
+  set.meta = c.take<uint32_t>(4 * N);
+  set.src = c.take<uint32_t>(4 * N);
   IQueue iq;
   const size_t NQ = (size_t)kNumQueues * N;
   iq.x = c.take<double>(NQ);
@@ -181,8 +180,27 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   uint32_t* si = c.take<uint32_t>(E);
   double* sout = c.take<double>(E * (B + 5));
   if (!x) return;
+  x->set = set;
   for (int cl = 0; cl < 2; ++cl)
-    for (int b = 0; b < 2; ++b) x->pool[cl][b] = pools[cl][b];
+    for (int b = 0; b < 2; ++b) {
+      const size_t o = (size_t)(2 * cl + b) * N;
+      Pool& p = x->pool[cl][b];
+      p.x = set.x + o;
+      p.y = set.y + o;
+      p.z = set.z + o;
+      p.u = set.u + o;
+      p.v = set.v + o;
+      p.w = set.w + o;
+      p.T = set.T + o;
+      p.nlam = set.nlam + o;
+      p.k0 = set.k0 + o;
+      p.k1 = set.k1 + o;
+      p.k2 = set.k2 + o;
+      p.evt = set.evt + o;
+      p.nstep = set.nstep + o;
+      p.meta = set.meta + o;
+      p.src = set.src + o;
+    }
   x->iq = iq;
   x->tab_d = tab_d;
   x->tab_f = tab_f;
@@ -213,7 +231,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
 
 bool config_ok(const ems_config* c) {
   return c && c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && c->max_events >= 1 &&
-         c->max_bins >= 1 && c->queue_capacity >= 1 &&
+         c->max_bins >= 1 && c->queue_capacity >= 1 && c->iterations_per_sync <= kMaxPerSync &&
          (c->precision == EMS_FP64 || c->precision == EMS_MIXED);
 }
 
@@ -274,11 +292,13 @@ ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, em
     delete x;
     return fail(EMS_E_HIP, std::string("ems_create: pinned host buffer: ") + hipGetErrorString(e));
   }
+  x->per_sync = cfg->iterations_per_sync == 0 ? 8 : (int)cfg->iterations_per_sync;
   if (cfg->flags & EMS_FLAG_TIME_STEPS) {
-    if (hipEventCreate(&x->ev0) != hipSuccess || hipEventCreate(&x->ev1) != hipSuccess) {
-      ems_destroy(x);
-      return fail(EMS_E_HIP, "ems_create: hipEventCreate failed");
-    }
+    for (int j = 0; j < 2 * x->per_sync; ++j)
+      if (hipEventCreate(&x->ev[j]) != hipSuccess) {
+        ems_destroy(x);
+        return fail(EMS_E_HIP, "ems_create: hipEventCreate failed");
+      }
   }
   reset_events(x);
   *out = x;
@@ -289,8 +309,8 @@ void ems_destroy(ems_ctx* x) {
   if (!x) return;
   if (x->h_ctr) (void)hipHostFree(x->h_ctr);
   if (x->h_done) (void)hipHostFree(x->h_done);
-  if (x->ev0) (void)hipEventDestroy(x->ev0);
-  if (x->ev1) (void)hipEventDestroy(x->ev1);
+  for (hipEvent_t e : x->ev)
+    if (e) (void)hipEventDestroy(e);
   delete x;
 }
 
@@ -356,7 +376,8 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
     return fail(EMS_E_ARG, "init_geometry: slab half widths must be positive");
   if (g->kind == EMS_GEOM_CYLINDERS && !(g->half_z > 0 && g->bounds[0] == 0.0))
     return fail(EMS_E_ARG, "init_geometry: shells need half_z > 0 and a first radius of 0");
-  if (g->bz != 0.0) return fail(EMS_E_ARG, "init_geometry: magnetic field not supported yet");
+  if (g->bz != 0.0 && !(g->field_tol > 0.0))
+    return fail(EMS_E_ARG, "init_geometry: a field needs a positive field_tol");
   hipStream_t s = (hipStream_t)stream;
   HIP_OK(hipMemcpyAsync(x->geo_bounds, g->bounds, sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(x->geo_mat, g->material, sizeof(int) * g->n_vol, hipMemcpyHostToDevice, s));
@@ -464,7 +485,7 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
   }
   *m_out = m;
   if (m == 0) return EMS_OK;
-  HIP_OK(launch_admit(x->P, x->q, x->pool[0][x->cur], x->pool[1][x->cur], x->q_head, m, s));
+  HIP_OK(launch_admit(x->P, x->q, x->set, x->cfg.pool_capacity, x->cur, x->q_head, m, s));
   x->q_head = (x->q_head + m) % x->q.capacity;
   x->q_count -= m;
   x->pending_prims -= m;
@@ -473,54 +494,66 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
   return EMS_OK;
 }
 
-// One step iteration (admission, transport, interactions) and its readback.
-ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* stepped,
-                   uint64_t* deferred, bool admit_first) {
-  HIP_OK(launch_iter_begin(x->ctr, x->nG, x->nC, s));
+// One sync interval: up to `iters` iterations enqueued back to back (admission
+// only at its start), then one readback of the counters.  Pool sizes, the
+// deferral bound and the queue sizes stay on the device between iterations.
+struct IntervalOut {
+  uint64_t stepped = 0, deferred = 0, busy = 0, peak = 0;
+};
+
+ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
+                        bool admit_first, IntervalOut* io) {
+  HIP_OK(launch_iter_begin(x->ctr, true, x->nG, x->nC, s));
   if (admit_first) {
     uint32_t m = 0;
     const ems_status st = admit(x, s, &m);
     if (st != EMS_OK) return st;
   }
-  const uint32_t nG = x->nG, nC = x->nC, n = nG + nC;
-  if (n == 0) {
+  if (x->nG + x->nC == 0) {
     if (admit_first && !x->pending.empty())
       return fail(EMS_E_INTERNAL, "transport_events: queued events could not be admitted");
     return EMS_OK;
   }
   const uint32_t cap = x->cfg.pool_capacity;
-  // every stepped track leaves at most three tracks, so n + 2k <= cap bounds both pools
-  const uint32_t k = std::min<uint64_t>(n, (uint64_t)(cap - n) / 2);
-  if (k == 0) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
-  const uint32_t kG = std::min(nG, k), kC = std::min(nC, k - kG);
-  if (x->ev0) HIP_OK(hipEventRecord(x->ev0, s));
-  HIP_OK(launch_iteration(x->P, x->pool[0][x->cur], x->pool[1][x->cur], nG, kG, nC, kC,
-                          x->pool[0][1 - x->cur], x->pool[1][1 - x->cur], x->iq,
-                          x->cfg.precision == EMS_MIXED, rec, s));
-  if (x->ev1) HIP_OK(hipEventRecord(x->ev1, s));
+  const bool mixed = x->cfg.precision == EMS_MIXED;
+  // every stepped track leaves at most three, and the pool never exceeds its capacity
+  uint64_t bound = (uint64_t)x->nG + x->nC;
+  for (int j = 0; j < iters; ++j) {
+    if (j > 0) {
+      HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
+      bound = std::min<uint64_t>(cap, 3 * bound);
+    }
+    if (x->ev[2 * j]) HIP_OK(hipEventRecord(x->ev[2 * j], s));
+    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, (uint32_t)bound, mixed, rec, s));
+    if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
+    x->cur = 1 - x->cur;
+  }
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const unsigned long long* L = x->h_ctr;
+  const unsigned long long* S = L + kLStats * kLineWords;
   const uint32_t outG = (uint32_t)L[kLOut * kLineWords], outC = (uint32_t)(L[kLOut * kLineWords] >> 32);
   const uint32_t n_done = std::min((uint32_t)L[kLDone * kLineWords], x->cfg.max_events);
   const uint64_t pos_steps = L[kLPosSteps * kLineWords];
-  x->run_steps[EMS_GAMMA] += kG;
-  x->run_steps[EMS_POSITRON] += pos_steps;
-  x->run_steps[EMS_ELECTRON] += kC - pos_steps;
-  x->stats.launches += 1;
-  x->stats.tracks_in += n;
-  x->stats.tracks_out += (uint64_t)outG + outC;
-  uint64_t queued = 0;
-  for (int q = 0; q < kNumQueues; ++q) {
-    const unsigned long long v = L[(kLQueue + q / 2) * kLineWords];
-    queued += (q & 1) ? (v >> 32) : (v & 0xFFFFFFFFull);
+  uint64_t queued_last = 0;
+  for (int l = 0; l < 4; ++l) {
+    const unsigned long long v = L[(kLQueue + l) * kLineWords];
+    queued_last += (v & 0xFFFFFFFFull) + (v >> 32);
   }
-  x->stats.queued += queued;
-  if (x->ev0) {
-    float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, x->ev0, x->ev1));
-    x->stats.kernel_ms += ms;
+  x->run_steps[EMS_GAMMA] += S[kSStepG];
+  x->run_steps[EMS_POSITRON] += pos_steps;
+  x->run_steps[EMS_ELECTRON] += S[kSStepC] - pos_steps;
+  x->stats.launches += S[kSBusy];
+  x->stats.tracks_in += S[kSIn];
+  x->stats.tracks_out += S[kSOut] + outG + outC;
+  x->stats.queued += S[kSQueued] + queued_last;
+  if (x->ev[0]) {
+    for (int j = 0; j < iters; ++j) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, x->ev[2 * j], x->ev[2 * j + 1]));
+      x->stats.kernel_ms += ms;
+    }
   }
   if (n_done) {
     HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, n_done * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -536,9 +569,11 @@ ems_status iterate(ems_ctx* x, hipStream_t s, ems_step_record* rec, uint64_t* st
   }
   x->nG = outG;
   x->nC = outC;
-  x->cur = 1 - x->cur;
-  *stepped += k;
-  *deferred += n - k;
+  io->stepped += S[kSStepped];
+  io->deferred += S[kSIn] - S[kSStepped];
+  io->busy += S[kSBusy];
+  io->peak = std::max<uint64_t>(io->peak, S[kSPeak]);
+  if (S[kSStall]) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
   return EMS_OK;
 }
 
@@ -555,19 +590,24 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
     const ems_status st = submit(x, b, s);
     if (st != EMS_OK) return st;
   }
-  uint64_t it = 0, stepped = 0, deferred = 0, peak = (uint64_t)x->nG + x->nC;
+  uint64_t it = 0;
+  IntervalOut io;
+  io.peak = (uint64_t)x->nG + x->nC;
+  const int per_sync = x->per_sync;
   while (max_iterations < 0 || it < (uint64_t)max_iterations) {
     if (x->nG + x->nC == 0 && x->pending.empty()) break;
-    const ems_status st = iterate(x, s, nullptr, &stepped, &deferred, true);
+    int k = per_sync;
+    if (max_iterations >= 0) k = (int)std::min<uint64_t>((uint64_t)k, (uint64_t)max_iterations - it);
+    const ems_status st = run_interval(x, s, nullptr, k, true, &io);
     if (st != EMS_OK) return st;
-    peak = std::max<uint64_t>(peak, (uint64_t)x->nG + x->nC);
-    ++it;
+    it += k;
   }
+  const uint64_t stepped = io.stepped, deferred = io.deferred, peak = io.peak;
   if (progress) {
     progress->alive = (uint64_t)x->nG + x->nC;
     progress->queued_primaries = x->pending_prims;
     progress->queued_events = x->pending.size();
-    progress->iterations = it;
+    progress->iterations = io.busy;
     progress->track_steps = stepped;
     progress->deferred = deferred;
     progress->peak_alive = peak;
@@ -651,15 +691,15 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   // every slot of this context is reset: step_once discards any events in flight
   reset_events(x);
   HIP_OK(launch_slots_reset(x->P, s));
-  HIP_OK(launch_iter_begin(x->ctr, 0, 0, s));
-  HIP_OK(launch_pool_load(x->P, x->pool[0][0], x->pool[1][0], *in, n, s));
+  HIP_OK(launch_iter_begin(x->ctr, true, 0, 0, s));
+  HIP_OK(launch_pool_load(x->P, x->set, x->cfg.pool_capacity, *in, n, s));
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   x->nG = (uint32_t)x->h_ctr[kLAdmit * kLineWords];
   x->nC = (uint32_t)(x->h_ctr[kLAdmit * kLineWords] >> 32);
-  uint64_t stepped = 0, deferred = 0;
-  ems_status st = iterate(x, s, rec, &stepped, &deferred, false);
+  IntervalOut io;
+  ems_status st = run_interval(x, s, rec, 1, false, &io);
   if (st != EMS_OK) return st;
   HIP_OK(launch_pool_dump(x->pool[0][x->cur], *out, x->nG, 0, s));
   HIP_OK(launch_pool_dump(x->pool[1][x->cur], *out, x->nC, x->nG, s));

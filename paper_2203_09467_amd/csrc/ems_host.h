@@ -11,12 +11,11 @@ namespace ems {
 int build_physics_tables(const ems_material* mats, int n_mats, const ems_physics_options& o,
                          std::vector<double>& tab, MatParams* mp);
 
-hipError_t launch_iteration(const Params& P, const Pool& inG, const Pool& inC, uint32_t nG,
-                            uint32_t kG, uint32_t nC, uint32_t kC, const Pool& outG,
-                            const Pool& outC, const IQueue& Q, bool mixed, ems_step_record* rec,
-                            hipStream_t s);
-hipError_t launch_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC, hipStream_t s);
-hipError_t launch_admit(const Params& P, const Queue& q, const Pool& poolG, const Pool& poolC,
+hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur, const IQueue& Q,
+                            uint32_t bound, bool mixed, ems_step_record* rec, hipStream_t s);
+hipError_t launch_iter_begin(unsigned long long* ctr, bool explicit_counts, uint32_t nG,
+                             uint32_t nC, hipStream_t s);
+hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t N, int cur,
                         uint32_t head, uint32_t m, hipStream_t s);
 hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, const uint32_t* slots,
                           const uint32_t* ids, uint32_t n_events, const int32_t* sp,
@@ -28,8 +27,8 @@ hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t
 hipError_t launch_slots_reset(const Params& P, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t s);
-hipError_t launch_pool_load(const Params& P, const Pool& pg, const Pool& pc,
-                            const ems_track_soa& src, uint32_t n, hipStream_t s);
+hipError_t launch_pool_load(const Params& P, const Pool& S, uint32_t N, const ems_track_soa& src,
+                            uint32_t n, hipStream_t s);
 hipError_t launch_pool_dump(const Pool& p, const ems_track_soa& dst, uint32_t n, uint32_t off,
                             hipStream_t s);
 hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_t n,

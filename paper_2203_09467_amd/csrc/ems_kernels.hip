@@ -225,6 +225,7 @@ __device__ __forceinline__ int locate(const Params& P, double x, double y, doubl
 __device__ __forceinline__ double distance(const Params& P, int vol, double px, double py,
                                            double pz, double dx, double dy, double dz,
                                            int& next) {
+#pragma clang fp contract(off)
   double s = HUGE_VAL;
   int nx = -1;
   if (P.gkind == EMS_GEOM_SLABS) {
@@ -330,6 +331,118 @@ __device__ __forceinline__ void mom_diff(double a, double ax, double ay, double 
   }
 }
 
+// ------------------------------------------------------------------ magnetic field
+
+// Charged tracks in a uniform field B_z, always in FP64: dr/ds = d,
+// dd/ds = kappa (d_y, -d_x, 0), kappa = 2.99792458 q B_z / p (1/cm, MeV/c, tesla).
+constexpr int kFieldMaxSub = 10000;
+constexpr double kFieldHmin = 1.0e-9;
+constexpr double kFieldVacuumPath = 1000.0;
+
+// One classical fourth-order Runge-Kutta step of length h.  The field-step
+// decisions (error against tolerance, chord against boundary) compare differences
+// of nearly equal positions, so every operation here and in field_move() and
+// distance() is evaluated unfused, in the order the equations are written:
+// then both decisions and results are those of IEEE FP64 arithmetic, independent
+// of how the compiler schedules the code.
+__device__ __forceinline__ void rk4(double kappa, double h, double rx, double ry, double rz,
+                                    double dx, double dy, double dz, double& ox, double& oy,
+                                    double& oz, double& ex, double& ey, double& ez) {
+#pragma clang fp contract(off)
+  const double hh = 0.5 * h;
+  // stage k: position derivative t_k, direction derivative kappa (t_k,y, -t_k,x, 0)
+  const double g1x = kappa * dy, g1y = -kappa * dx;
+  const double t2x = dx + hh * g1x, t2y = dy + hh * g1y;
+  const double g2x = kappa * t2y, g2y = -kappa * t2x;
+  const double t3x = dx + hh * g2x, t3y = dy + hh * g2y;
+  const double g3x = kappa * t3y, g3y = -kappa * t3x;
+  const double t4x = dx + h * g3x, t4y = dy + h * g3y;
+  const double g4x = kappa * t4y, g4y = -kappa * t4x;
+  const double h6 = h / 6.0;
+  ox = rx + h6 * (dx + 2.0 * t2x + 2.0 * t3x + t4x);
+  oy = ry + h6 * (dy + 2.0 * t2y + 2.0 * t3y + t4y);
+  oz = rz + h6 * (dz + 2.0 * dz + 2.0 * dz + dz);
+  ex = dx + h6 * (g1x + 2.0 * g2x + 2.0 * g3x + g4x);
+  ey = dy + h6 * (g1y + 2.0 * g2y + 2.0 * g3y + g4y);
+  ez = dz + h6 * 0.0;
+}
+
+// Curved move within volume `vol` for at most s_max (maybe infinite): substeps
+// with step-doubling error control, the boundary searched on each substep's chord
+// and accepted once the chord's sagitta is within tolerance.  Returns 0 at s_max,
+// 1 at a boundary (next set), 2 for a looper (vacuum path cap or substep cap).
+__device__ __forceinline__ int field_move(const Params& P, int vol, double kappa, double s_max,
+                                          bool vacuum, double& x, double& y, double& z,
+                                          double& u, double& v, double& w, double& s_out,
+                                          int& next) {
+#pragma clang fp contract(off)
+  const double tol = P.ftol;
+  const double limit = vacuum ? fmin(s_max, kFieldVacuumPath) : s_max;
+  double travelled = 0.0;
+  double h = fabs(kappa) > 0.0 ? fmin(limit, 1.0 / fabs(kappa)) : limit;
+  next = -1;
+  for (int nsub = 0; nsub < kFieldMaxSub; ++nsub) {
+    const double hh = fmin(h, limit - travelled);
+    double fx, fy, fz, fu, fv, fw, mx, my, mz, mu, mv, mw, px, py, pz, pu, pv, pw;
+    rk4(kappa, hh, x, y, z, u, v, w, fx, fy, fz, fu, fv, fw);
+    rk4(kappa, 0.5 * hh, x, y, z, u, v, w, mx, my, mz, mu, mv, mw);
+    rk4(kappa, 0.5 * hh, mx, my, mz, mu, mv, mw, px, py, pz, pu, pv, pw);
+    const double err = sqrt((px - fx) * (px - fx) + (py - fy) * (py - fy) + (pz - fz) * (pz - fz));
+    if (err > tol && hh > kFieldHmin) {
+      h = 0.5 * hh;
+      continue;
+    }
+    double cx = px - x, cy = py - y, cz = pz - z;
+    const double L = sqrt(cx * cx + cy * cy + cz * cz);
+    int nx = -1;
+    double sb = HUGE_VAL;
+    if (L > 0.0) {
+      cx /= L;
+      cy /= L;
+      cz /= L;
+      sb = distance(P, vol, x, y, z, cx, cy, cz, nx);
+    }
+    if (sb < L) {
+      const double qx = mx - x, qy = my - y, qz = mz - z;
+      const double along = qx * cx + qy * cy + qz * cz;
+      const double sx = qx - along * cx, sy = qy - along * cy, sz = qz - along * cz;
+      const double sag = sqrt(sx * sx + sy * sy + sz * sz);
+      if (sag <= tol || hh <= kFieldHmin) {
+        const double part = hh * (sb / L);
+        double ox, oy, oz, du, dv, dw;
+        rk4(kappa, part, x, y, z, u, v, w, ox, oy, oz, du, dv, dw);
+        x += sb * cx;
+        y += sb * cy;
+        z += sb * cz;
+        const double n = sqrt(du * du + dv * dv + dw * dw);
+        u = du / n;
+        v = dv / n;
+        w = dw / n;
+        s_out = travelled + part;
+        next = nx;
+        return 1;
+      }
+      h = fmax(hh * (sb / L), kFieldHmin);
+      continue;
+    }
+    x = px;
+    y = py;
+    z = pz;
+    const double n = sqrt(pu * pu + pv * pv + pw * pw);
+    u = pu / n;
+    v = pv / n;
+    w = pw / n;
+    travelled += hh;
+    if (travelled >= limit) {
+      s_out = travelled;
+      return limit < s_max ? 2 : 0;
+    }
+    h = err < tol / 32.0 ? 2.0 * hh : hh;
+  }
+  s_out = travelled;
+  return 2;
+}
+
 // ------------------------------------------------------------------ track records
 
 struct Track {
@@ -427,7 +540,7 @@ struct Moved {
 // escape, process selection (u_1 against Sigma_i(T')), cutoffs.  A track whose
 // step ends in an interaction (or a positron that stops) is sent to a queue with
 // its step count not yet incremented; every other survivor's count is incremented.
-template <class R>
+template <class R, bool FIELD>
 __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   const double INF = HUGE_VAL;
   const int sp = t.sp;
@@ -464,24 +577,32 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   }
 
   int next;
-  const double s_geo = distance(P, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
   int lim;
   double s;
-  if (s_geo <= s_phys && s_geo <= s_cont) {
-    lim = 0;
-    s = s_geo;
-  } else if (s_phys <= s_cont) {
-    lim = 1;
-    s = s_phys;
+  if (FIELD && charged) {  // curved path up to the physics limit; a boundary met first wins
+    const double p = sqrt(t.T * (t.T + 2.0 * kMe));
+    const double kappa = 2.99792458 * (sp == EMS_ELECTRON ? -1.0 : 1.0) * P.bz / p;
+    const int res = field_move(P, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
+                               t.u, t.v, t.w, s, next);
+    lim = res == 1 ? 0 : (res == 2 ? 3 : (s_phys <= s_cont ? 1 : 2));
   } else {
-    lim = 2;
-    s = s_cont;
+    const double s_geo = distance(P, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
+    if (s_geo <= s_phys && s_geo <= s_cont) {
+      lim = 0;
+      s = s_geo;
+    } else if (s_phys <= s_cont) {
+      lim = 1;
+      s = s_phys;
+    } else {
+      lim = 2;
+      s = s_cont;
+    }
+    t.x += s * t.u;
+    t.y += s * t.v;
+    t.z += s * t.w;
   }
   o.limiter = lim;
   o.step_len = s;
-  t.x += s * t.u;
-  t.y += s * t.v;
-  t.z += s * t.w;
 
   const double T0 = t.T;
   double T1 = T0;
@@ -511,6 +632,9 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   } else if (charged && T1 < P.tcut) {
     o.dep += T1;
     o.dest = sp == EMS_POSITRON ? kQRest : -2;
+  } else if (lim == 3) {  // looper
+    o.killed += T1;
+    o.dest = -2;
   } else if (lim == 0) {
     if (next < 0) {
       o.esc += T1;
@@ -742,7 +866,7 @@ __device__ __forceinline__ uint32_t queue_size(const Params& P, int q) {
   return (q & 1) ? hi32(v) : lo32(v);
 }
 
-__device__ __forceinline__ void write_track(const Pool& p, uint32_t j, int sp, int vol, double x,
+__device__ __forceinline__ void write_track(const Pool& p, size_t j, int sp, int vol, double x,
                                             double y, double z, double u, double v, double w,
                                             double T, double nlam, uint32_t k0, uint32_t k1,
                                             uint32_t k2, uint32_t evt, uint32_t nstep) {
@@ -762,15 +886,10 @@ __device__ __forceinline__ void write_track(const Pool& p, uint32_t j, int sp, i
   p.meta[j] = (uint32_t)sp | ((uint32_t)vol << 2);
 }
 
-// write_track into one of two pools chosen per lane (a branch, not a select of
-// pool descriptors, which would be spilled)
-__device__ __forceinline__ void write_either(bool g, const Pool& pg, const Pool& pc, uint32_t j,
-                                             int sp, int vol, double x, double y, double z,
-                                             double u, double v, double w, double T, double nlam,
-                                             uint32_t k0, uint32_t k1, uint32_t k2, uint32_t evt,
-                                             uint32_t nstep) {
-  if (g) write_track(pg, j, sp, vol, x, y, z, u, v, w, T, nlam, k0, k1, k2, evt, nstep);
-  else write_track(pc, j, sp, vol, x, y, z, u, v, w, T, nlam, k0, k1, k2, evt, nstep);
+// Element offset of pool buffer (class, parity) in the pool set: for every field
+// the four buffers are consecutive, photon buffers first.
+__device__ __forceinline__ size_t buf_off(bool charged, int parity, uint32_t N) {
+  return (size_t)((charged ? 2 : 0) + parity) * N;
 }
 
 __device__ __forceinline__ unsigned long long fixed_point(double e, double scale) {
@@ -786,21 +905,21 @@ __device__ __forceinline__ void count_done(const Params& P, uint32_t e, int delt
   }
 }
 
-// One iteration, part 1.  Blocks [0, nbG) step the photon pool, the rest the
-// charged pool (so every wavefront holds one species class).  In each pool the
-// first k tracks are stepped and the rest copied unchanged (deferred for lack of
-// output room).  Survivors go to the output pool of their class, tracks that
-// interact to their process queue; both are allocated one atomic per wavefront.
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool inC, uint32_t nG,
-                                                      uint32_t kG, uint32_t nC, uint32_t kC,
-                                                      uint32_t nbG, Pool outG, Pool outC,
-                                                      IQueue Q, ems_step_record* rec) {
-  const bool cblk = blockIdx.x >= nbG;
-  const Pool& in = cblk ? inC : inG;
-  const Pool& out = cblk ? outC : outG;
+// One iteration, part 1, for chunk c of kBlock tracks: chunks [0, nbG) of the
+// photon pool, then the charged pool (so every wavefront holds one species class).
+// In each pool the first k tracks are stepped and the rest copied unchanged
+// (deferred for lack of output room).  Survivors go to the output pool of their
+// class, tracks that interact to their process queue; both are reserved once per
+// block.
+template <class R, bool FIELD>
+__device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
+                                                const IQueue& Q, ems_step_record* rec,
+                                                uint32_t c, uint32_t nG, uint32_t kG, uint32_t nC,
+                                                uint32_t kC, uint32_t nbG) {
+  const bool cblk = c >= nbG;
+  const size_t io = buf_off(cblk, cur, N), oo = buf_off(cblk, 1 - cur, N);
   const uint32_t n = cblk ? nC : nG, k = cblk ? kC : kG;
-  const uint32_t i = (blockIdx.x - (cblk ? nbG : 0u)) * kBlock + threadIdx.x;
+  const uint32_t i = (c - (cblk ? nbG : 0u)) * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = i < n;
   Track t{};
@@ -810,27 +929,27 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
   bool stepped = false, usable = valid, vol_out = false;
   uint32_t vol = 0;
   if (valid) {
-    const uint32_t meta = in.meta[i];
+    const uint32_t meta = S.meta[io + i];
     t.sp = (int)(meta & 3u);
     vol = meta >> 2;
-    t.evt = in.evt[i];
+    t.evt = S.evt[io + i];
     // a state that names no species, volume or event slot of this run is dropped
     usable = t.sp <= 2 && (vol == kVolOut || vol < (uint32_t)P.nvol) && t.evt < P.max_events;
   }
   if (usable) {
-    t.x = in.x[i];
-    t.y = in.y[i];
-    t.z = in.z[i];
-    t.u = in.u[i];
-    t.v = in.v[i];
-    t.w = in.w[i];
-    t.T = in.T[i];
-    t.nlam = in.nlam[i];
-    t.k0 = in.k0[i];
-    t.k1 = in.k1[i];
-    t.k2 = in.k2[i];
-    t.nstep = in.nstep[i];
-    t.src = rec ? in.src[i] : 0u;
+    t.x = S.x[io + i];
+    t.y = S.y[io + i];
+    t.z = S.z[io + i];
+    t.u = S.u[io + i];
+    t.v = S.v[io + i];
+    t.w = S.w[io + i];
+    t.T = S.T[io + i];
+    t.nlam = S.nlam[io + i];
+    t.k0 = S.k0[io + i];
+    t.k1 = S.k1[io + i];
+    t.k2 = S.k2[io + i];
+    t.nstep = S.nstep[io + i];
+    t.src = rec ? S.src[io + i] : 0u;
     if (vol == kVolOut) {  // primary born outside the world: escapes with no step
       vol_out = true;
       t.vol = 0;
@@ -839,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
     } else {
       t.vol = (int)vol;
       if (i < k) {
-        transport<R>(P, t, o);
+        transport<R, FIELD>(P, t, o);
         stepped = true;
       } else {
         o.dest = -1;  // deferred: copied unchanged
@@ -858,6 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) mq[q] = __ballot(o.dest == q);
   const uint64_t mpos = __ballot(stepped && t.sp == EMS_POSITRON);
+  __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
     sh_cnt[wave][0] = (uint32_t)__popcll(mS);
 #pragma unroll
@@ -894,9 +1014,9 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
   if (o.dest == -1) {
     uint32_t j = sh_base[0] + lanes_below(mS, lane);
     for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][0];
-    write_track(out, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, t.nlam, t.k0, t.k1, t.k2,
-                t.evt, t.nstep);
-    if (rec) out.src[j] = t.src;
+    write_track(S, oo + j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, t.nlam, t.k0, t.k1,
+                t.k2, t.evt, t.nstep);
+    if (rec) S.src[oo + j] = t.src;
   } else if (o.dest >= 0) {  // interacting track -> its process queue
     const int q = o.dest;
     uint64_t own = mq[0];
@@ -949,34 +1069,60 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool inG, Pool i
   }
 }
 
+// Part 1 as a kernel, one chunk per block: pool sizes come from the admission
+// cursors and the deferral bound k = min(n, (cap - n)/2) is taken on the device, so
+// the host launches an upper bound of blocks and the surplus exits at once.
+template <class R, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t N, int cur,
+                                                      IQueue Q, ems_step_record* rec,
+                                                      uint32_t cap) {
+  const unsigned long long a = *ctr_line(P, kLAdmit);
+  const uint32_t nG = lo32(a), nC = hi32(a), n = nG + nC;
+  const uint32_t k = n > cap ? 0u : min(n, (cap - n) / 2u);
+  const uint32_t kG = min(nG, k), kC = min(nC, k - kG);
+  const uint32_t nbG = (nG + kBlock - 1) / kBlock, nbC = (nC + kBlock - 1) / kBlock;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
+    unsigned long long* st = ctr_line(P, kLStats);
+    atomicAdd(&st[kSIn], (unsigned long long)n);
+    atomicAdd(&st[kSStepped], (unsigned long long)k);
+    atomicAdd(&st[kSStepG], (unsigned long long)kG);
+    atomicAdd(&st[kSStepC], (unsigned long long)kC);
+    atomicAdd(&st[kSBusy], 1ull);
+    atomicMax(&st[kSPeak], (unsigned long long)n);
+    if (k == 0) atomicAdd(&st[kSStall], 1ull);
+  }
+  if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
+  transport_chunk<R, FIELD>(P, S, N, cur, Q, rec, blockIdx.x, nG, kG, nC, kC, nbG);
+}
+
 // Wave-aggregated append of one output stream (parent or secondary j) into the
 // two class pools: per class a ballot, a rank and one atomic per wavefront.
 struct OutBase {
   uint32_t g, c;
 };
 
-// One iteration, part 2: the interactions.  Blocks are partitioned among the
-// queues (block-uniform process, so a wavefront runs one sampler); survivors and
-// secondaries go to the output pool of their class.
+// One iteration, part 2: the interactions, for virtual block v.  Virtual blocks
+// are partitioned among the queues (block-uniform process, so a wavefront runs
+// one sampler); survivors and secondaries go to the output pool of their class.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool outG, Pool outC,
-                                                     ems_step_record* rec) {
-  // block -> (queue, block within queue) from the queue sizes
+__device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q, const Pool& S,
+                                               uint32_t N, int cur, ems_step_record* rec,
+                                               uint32_t v) {
   uint32_t start = 0, qsel = kNumQueues, cnt = 0;
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) {
     const uint32_t c = queue_size(P, q);
     const uint32_t nb = (c + kBlock - 1) / kBlock;
-    if (qsel == kNumQueues && blockIdx.x < start + nb) {
+    if (qsel == kNumQueues && v < start + nb) {
       qsel = q;
       cnt = c;
     } else if (qsel == kNumQueues) {
       start += nb;
     }
   }
-  if (qsel == kNumQueues) return;  // whole block beyond the work
+  if (qsel == kNumQueues) return;  // (uniform) beyond the work
   const int q = (int)qsel;
-  const uint32_t i = (blockIdx.x - start) * kBlock + threadIdx.x;
+  const uint32_t i = (v - start) * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = i < cnt;
   Track t{};
@@ -1022,6 +1168,7 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
   __shared__ uint32_t sh_cnt[kW][2];
   __shared__ uint32_t sh_base[2];
   const int wave = threadIdx.x >> 6;
+  __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
     sh_cnt[wave][0] = ng0 + ng1 + ng2 + ng3;
     sh_cnt[wave][1] = nc0 + nc1 + nc2 + nc3;
@@ -1045,31 +1192,30 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
     bg += sh_cnt[w2][0];
     bc += sh_cnt[w2][1];
   }
+  const size_t offG = buf_off(false, 1 - cur, N), offC = buf_off(true, 1 - cur, N);
   if (h0) {
-    const uint32_t j = g0 ? bg + lanes_below(mg0, lane) : bc + lanes_below(mc0, lane);
-    write_either(g0, outG, outC, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, -1.0, t.k0,
-                t.k1, t.k2, t.evt, t.nstep);
-    if (rec) {
-      if (g0) outG.src[j] = t.src;
-      else outC.src[j] = t.src;
-    }
+    const size_t j = g0 ? offG + bg + lanes_below(mg0, lane) : offC + bc + lanes_below(mc0, lane);
+    write_track(S, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, -1.0, t.k0, t.k1, t.k2,
+                t.evt, t.nstep);
+    if (rec) S.src[j] = t.src;
   }
   if (h1) {
-    const uint32_t j = g1 ? bg + ng0 + lanes_below(mg1, lane) : bc + nc0 + lanes_below(mc1, lane);
-    write_either(g1, outG, outC, j, o.s0.sp, t.vol, t.x, t.y, t.z, o.s0.u, o.s0.v, o.s0.w, o.s0.T,
-                -1.0, o.s0.k0, o.s0.k1, o.s0.k2, t.evt, 0u);
+    const size_t j = g1 ? offG + bg + ng0 + lanes_below(mg1, lane)
+                        : offC + bc + nc0 + lanes_below(mc1, lane);
+    write_track(S, j, o.s0.sp, t.vol, t.x, t.y, t.z, o.s0.u, o.s0.v, o.s0.w, o.s0.T, -1.0,
+                o.s0.k0, o.s0.k1, o.s0.k2, t.evt, 0u);
   }
   if (h2) {
-    const uint32_t j = g2 ? bg + ng0 + ng1 + lanes_below(mg2, lane)
-                          : bc + nc0 + nc1 + lanes_below(mc2, lane);
-    write_either(g2, outG, outC, j, o.s1.sp, t.vol, t.x, t.y, t.z, o.s1.u, o.s1.v, o.s1.w, o.s1.T,
-                -1.0, o.s1.k0, o.s1.k1, o.s1.k2, t.evt, 0u);
+    const size_t j = g2 ? offG + bg + ng0 + ng1 + lanes_below(mg2, lane)
+                        : offC + bc + nc0 + nc1 + lanes_below(mc2, lane);
+    write_track(S, j, o.s1.sp, t.vol, t.x, t.y, t.z, o.s1.u, o.s1.v, o.s1.w, o.s1.T, -1.0,
+                o.s1.k0, o.s1.k1, o.s1.k2, t.evt, 0u);
   }
   if (h3) {
-    const uint32_t j = g3 ? bg + ng0 + ng1 + ng2 + lanes_below(mg3, lane)
-                          : bc + nc0 + nc1 + nc2 + lanes_below(mc3, lane);
-    write_either(g3, outG, outC, j, o.s2.sp, t.vol, t.x, t.y, t.z, o.s2.u, o.s2.v, o.s2.w, o.s2.T,
-                -1.0, o.s2.k0, o.s2.k1, o.s2.k2, t.evt, 0u);
+    const size_t j = g3 ? offG + bg + ng0 + ng1 + ng2 + lanes_below(mg3, lane)
+                        : offC + bc + nc0 + nc1 + nc2 + lanes_below(mc3, lane);
+    write_track(S, j, o.s2.sp, t.vol, t.x, t.y, t.z, o.s2.u, o.s2.v, o.s2.w, o.s2.T, -1.0,
+                o.s2.k0, o.s2.k1, o.s2.k2, t.evt, 0u);
   }
   if (!valid) return;
   const uint32_t e = t.evt;
@@ -1088,17 +1234,42 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool ou
   }
 }
 
-// Start of an iteration: clear the iteration counters and set the admission
-// cursors to the current pool sizes.
-__global__ void k_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC) {
+// Part 2 as a kernel, one virtual block of the queues per block.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool S, uint32_t N,
+                                                     int cur, ems_step_record* rec) {
+  interact_chunk<R>(P, Q, S, N, cur, rec, blockIdx.x);
+}
+
+// Start of an iteration.  explicit_counts: begin a sync interval -- clear every
+// counter line and set the admission cursors to (nG, nC).  Otherwise continue from
+// the previous iteration: its output counts become this iteration's pool sizes,
+// its output and queue sizes are added to the interval statistics and cleared.
+__global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint32_t nG,
+                             uint32_t nC) {
   const int j = threadIdx.x;
-  if (j < kNumLines * kLineWords)
-    ctr[j] = j == kLAdmit * kLineWords ? (((unsigned long long)nC << 32) | nG) : 0ull;
+  if (explicit_counts) {
+    if (j < kNumLines * kLineWords)
+      ctr[j] = j == kLAdmit * kLineWords ? (((unsigned long long)nC << 32) | nG) : 0ull;
+    return;
+  }
+  if (j != 0) return;
+  const unsigned long long out = ctr[kLOut * kLineWords];
+  unsigned long long queued = 0;
+  for (int l = 0; l < 4; ++l) {
+    const unsigned long long v = ctr[(kLQueue + l) * kLineWords];
+    queued += (v & 0xFFFFFFFFull) + (v >> 32);
+    ctr[(kLQueue + l) * kLineWords] = 0ull;
+  }
+  ctr[kLStats * kLineWords + kSOut] += (out & 0xFFFFFFFFull) + (out >> 32);
+  ctr[kLStats * kLineWords + kSQueued] += queued;
+  ctr[kLAdmit * kLineWords] = out;
+  ctr[kLOut * kLineWords] = 0ull;
 }
 
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
 // charged pool at the admission cursors (one atomic per wavefront and class).
-__global__ void k_admit(Params P, Queue q, Pool poolG, Pool poolC, uint32_t head, uint32_t m) {
+__global__ void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur, uint32_t head, uint32_t m) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = j < m;
@@ -1117,10 +1288,9 @@ __global__ void k_admit(Params P, Queue q, Pool poolG, Pool poolC, uint32_t head
   uint32_t a, b, cc, d;
   philox10(q.event_id[r], q.index[r], 0u, 0u, P.seed, 0x243F6A88u, a, b, cc, d);
   const int vol = locate(P, x, y, z, u, v, w);
-  const Pool& pool = g ? poolG : poolC;
-  const uint32_t k = g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane);
-  write_track(pool, k, sp, 0, x, y, z, u, v, w, q.T[r], -1.0, a, b, cc, q.slot[r], 0u);
-  pool.meta[k] = (uint32_t)sp | ((vol < 0 ? kVolOut : (uint32_t)vol) << 2);
+  const size_t k = buf_off(!g, cur, N) + (g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane));
+  write_track(S, k, sp, 0, x, y, z, u, v, w, q.T[r], -1.0, a, b, cc, q.slot[r], 0u);
+  S.meta[k] = (uint32_t)sp | ((vol < 0 ? kVolOut : (uint32_t)vol) << 2);
 }
 
 // Copy a batch's primaries into the ring at tail; row r belongs to the event e with
@@ -1204,7 +1374,7 @@ __global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
 
 // Diagnostics: external SoA <-> pool layout (states sorted into the two class
 // pools at the admission cursors; src remembers the input index).
-__global__ void k_pool_load(Params P, Pool pg, Pool pc, ems_track_soa s, uint32_t n) {
+__global__ void k_pool_load(Params P, Pool S, uint32_t N, ems_track_soa s, uint32_t n) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = j < n;
@@ -1218,11 +1388,10 @@ __global__ void k_pool_load(Params P, Pool pg, Pool pc, ems_track_soa s, uint32_
   old = __shfl(old, 0);
   const uint32_t bg = lo32(old), bc = hi32(old);
   if (!valid) return;
-  const Pool& p = g ? pg : pc;
-  const uint32_t k = g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane);
-  write_track(p, k, sp, s.vol[j], s.x[j], s.y[j], s.z[j], s.u[j], s.v[j], s.w[j], s.T[j],
+  const size_t k = buf_off(!g, 0, N) + (g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane));
+  write_track(S, k, sp, s.vol[j], s.x[j], s.y[j], s.z[j], s.u[j], s.v[j], s.w[j], s.T[j],
               s.nlam[j], s.k0[j], s.k1[j], s.k2[j], s.event[j], s.nstep[j]);
-  p.src[k] = j;
+  S.src[k] = j;
 }
 
 __global__ void k_pool_dump(Pool p, ems_track_soa s, uint32_t n, uint32_t off) {
@@ -1254,37 +1423,40 @@ namespace ems {
 
 static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
-hipError_t launch_iteration(const Params& P, const Pool& inG, const Pool& inC, uint32_t nG,
-                            uint32_t kG, uint32_t nC, uint32_t kC, const Pool& outG,
-                            const Pool& outC, const IQueue& Q, bool mixed, ems_step_record* rec,
-                            hipStream_t s) {
-  const uint32_t nbG = blocks_for(nG, kBlock), nbC = blocks_for(nC, kBlock);
-  if (nbG + nbC == 0) return hipSuccess;
+// One iteration: transport then interactions; `bound` is an upper bound of the pool
+// size (the sizes themselves stay on the device).
+hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur, const IQueue& Q,
+                            uint32_t bound, bool mixed, ems_step_record* rec, hipStream_t s) {
+  const uint32_t cap = N;
   const dim3 b(kBlock);
-  if (mixed)
-    hipLaunchKernelGGL(k_transport<float>, dim3(nbG + nbC), b, 0, s, P, inG, inC, nG, kG, nC, kC,
-                       nbG, outG, outC, Q, rec);
+  const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
+  const bool field = P.bz != 0.0;
+  if (mixed && field)
+    hipLaunchKernelGGL((k_transport<float, true>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
+  else if (mixed)
+    hipLaunchKernelGGL((k_transport<float, false>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
+  else if (field)
+    hipLaunchKernelGGL((k_transport<double, true>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
   else
-    hipLaunchKernelGGL(k_transport<double>, dim3(nbG + nbC), b, 0, s, P, inG, inC, nG, kG, nC,
-                       kC, nbG, outG, outC, Q, rec);
+    hipLaunchKernelGGL((k_transport<double, false>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // at most kG + kC queued tracks; each queue adds at most one partial block
-  const uint32_t nbI = blocks_for((uint64_t)kG + kC, kBlock) + kNumQueues;
-  if (mixed) hipLaunchKernelGGL(k_interact<float>, dim3(nbI), b, 0, s, P, Q, outG, outC, rec);
-  else hipLaunchKernelGGL(k_interact<double>, dim3(nbI), b, 0, s, P, Q, outG, outC, rec);
+  if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec);
+  else hipLaunchKernelGGL(k_interact<double>, gI, b, 0, s, P, Q, S, N, cur, rec);
   return hipGetLastError();
 }
 
-hipError_t launch_iter_begin(unsigned long long* ctr, uint32_t nG, uint32_t nC, hipStream_t s) {
-  hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(kNumLines * kLineWords), 0, s, ctr, nG, nC);
+hipError_t launch_iter_begin(unsigned long long* ctr, bool explicit_counts, uint32_t nG,
+                             uint32_t nC, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(kNumLines * kLineWords), 0, s, ctr,
+                     explicit_counts ? 1 : 0, nG, nC);
   return hipGetLastError();
 }
 
-hipError_t launch_admit(const Params& P, const Queue& q, const Pool& poolG, const Pool& poolC,
+hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t N, int cur,
                         uint32_t head, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, q, poolG, poolC, head, m);
+  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, q, S, N, cur, head, m);
   return hipGetLastError();
 }
 
@@ -1324,10 +1496,10 @@ hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pool_load(const Params& P, const Pool& pg, const Pool& pc,
-                            const ems_track_soa& src, uint32_t n, hipStream_t s) {
+hipError_t launch_pool_load(const Params& P, const Pool& S, uint32_t N, const ems_track_soa& src,
+                            uint32_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_load, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, pg, pc, src, n);
+  hipLaunchKernelGGL(k_pool_load, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, S, N, src, n);
   return hipGetLastError();
 }
 

@@ -30,11 +30,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_workspace_size_and_argument_errors_without_gpu():
     import paper_2203_09467_amd as ems
-    cfg = ems.Config(1 << 16, 128, 100, 1 << 16, 1, ems.EMS_FP64, 0.0, 0)
+    cfg = ems.Config(1 << 16, 128, 100, 1 << 16, 1, ems.EMS_FP64, 0.0, 0, 0)
     n = ems.workspace_bytes(cfg)
     # two pool buffers of 88 B per slot dominate
     assert n >= 2 * 88 * (1 << 16)
-    bad = ems.Config(8, 128, 100, 1 << 16, 1, ems.EMS_FP64, 0.0, 0)
+    bad = ems.Config(8, 128, 100, 1 << 16, 1, ems.EMS_FP64, 0.0, 0, 0)
     assert ems.workspace_bytes(bad) == 0
     h = ctypes.c_void_p()
     st = ems._lib.ems_create(ctypes.byref(cfg), None, n, ctypes.byref(h))

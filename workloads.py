@@ -245,14 +245,36 @@ def serving(n_events: int = 1000, rate_hz: float = 50.0, seed: int = 5,
 
 def random_track_states(n: int, n_vol: int, seed: int, e_lo: float = 0.01, e_hi: float = 1.0e5,
                         species: Optional[np.ndarray] = None, vol_material=None,
-                        bounds=None, half_xy: float = 20.0) -> Dict[str, np.ndarray]:
+                        bounds=None, half_xy: float = 20.0, kind: int = 0,
+                        half_z: float = 0.0) -> Dict[str, np.ndarray]:
     """Random single-step inputs: species, log-uniform energy, a volume, a point
-    inside it (slabs), an isotropic direction, a random key and step count, and
-    interaction lengths left (half of them unset)."""
+    inside it (slabs: z between its planes; shells: radius between its radii), an
+    isotropic direction, a random key and step count, and interaction lengths left
+    (half of them unset).  A quarter of the states sit exactly on the volume's lower
+    surface, entering it."""
     rng = np.random.default_rng(seed)
     sp = rng.integers(0, 3, n).astype(np.int32) if species is None else species.astype(np.int32)
     T = _log_uniform(rng, n, e_lo, e_hi)
     vol = rng.integers(0, n_vol, n).astype(np.int32)
+    if kind == 1:
+        lo, hi = bounds[vol], bounds[vol + 1]
+        r = lo + (hi - lo) * rng.random(n)
+        on = (rng.random(n) < 0.25) & (lo > 0)
+        r = np.where(on, lo, r)
+        a = 2.0 * np.pi * rng.random(n)
+        pos = np.stack([r * np.cos(a), r * np.sin(a), (2.0 * rng.random(n) - 1.0) * half_z], axis=1)
+        cost = 2.0 * rng.random(n) - 1.0
+        phi = 2.0 * np.pi * rng.random(n)
+        sint = np.sqrt(1.0 - cost * cost)
+        d = np.stack([sint * np.cos(phi), sint * np.sin(phi), cost], axis=1)
+        outward = pos[:, 0] * d[:, 0] + pos[:, 1] * d[:, 1] >= 0
+        flip = on & ~outward
+        d[flip, :2] = -d[flip, :2]
+        nlam = np.where(rng.random(n) < 0.5, -1.0, rng.exponential(1.0, n))
+        key = rng.integers(0, 2**32, size=(n, 3), dtype=np.uint64).astype(np.uint32)
+        nstep = rng.integers(0, 1000, n).astype(np.uint32)
+        return dict(species=sp, energy=T, vol=vol, pos=pos, dir=d, nlam=nlam, key=key,
+                    nstep=nstep, event=np.arange(n, dtype=np.uint32))
     if bounds is not None:
         lo, hi = bounds[vol], bounds[vol + 1]
         z = lo + (hi - lo) * rng.random(n)
