@@ -76,7 +76,8 @@ def run_transport(ems, wl, n_events, args, precision, log_name):
     n_steps = args.warmup + args.steps
     ctx = ems.Context(pool_capacity=args.pool, max_events=n_events * n_steps,
                       max_bins=wl.geometry.n_bins, queue_capacity=n_events, seed=wl.seed,
-                      precision=precision, energy_budget=args.budget, time_steps=True)
+                      precision=precision, energy_budget=args.budget, time_steps=True,
+                      iterations_per_sync=args.per_sync)
     ctx.setup(wl.materials, wl.options, wl.geometry)
     batches = []
     for j in range(n_steps):
@@ -122,9 +123,9 @@ def run_serving(ems, args, precision):
     ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
                       max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
                       seed=wl.seed, precision=precision, energy_budget=args.budget,
-                      iterations_per_sync=4)
+                      iterations_per_sync=min(args.per_sync, args.serve_iters))
     ctx.setup(wl.materials, wl.options, wl.geometry)
-    res = serve(ctx, wl.events, iterations=4, time_limit=300.0)
+    res = serve(ctx, wl.events, iterations=args.serve_iters, time_limit=300.0)
     ctx.close()
     e_mean = float(wl.events.energy.sum() / wl.events.n_events)
     return {"p50_ms": res["p50"] * 1e3, "p99_ms": res["p99"] * 1e3,
@@ -144,11 +145,15 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool", type=int, default=1 << 24)
     ap.add_argument("--budget", type=float, default=2.5e7, help="energy in flight, MeV")
+    ap.add_argument("--per-sync", type=int, default=8,
+                    help="step iterations launched back to back between host synchronisations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-events", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
+    ap.add_argument("--serve-iters", type=int, default=32,
+                    help="step iterations per transport call of the serving loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times, "
                          "to scale HBM byte counters")

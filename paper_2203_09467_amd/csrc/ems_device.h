@@ -20,6 +20,7 @@ constexpr uint32_t kVolOut = 0x3FFFFFFFu;  // meta volume of a primary that star
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
 constexpr int kBlock = 512;
+constexpr uint32_t kStageMaxBytes = 64u * 1024u;  // per-block LDS budget of the staged run data
 
 // Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.  Photons and
 // charged tracks live in separate pools so that a wavefront steps one species

@@ -128,6 +128,24 @@ struct Px<float> {
 
 // ------------------------------------------------------------------ tables
 
+// Run data read during a step: the cross-section/range table of (material m,
+// species sp), volume bounds, volume -> material and volume -> tally-bin maps and
+// the material parameters.  The step kernels address them either in global memory
+// or in a copy staged in LDS by each block (the tables of the block's species
+// class only, so a staged table starts at species sp0).
+template <class R>
+struct View {
+  const R* tab;
+  int mstride, sp0;  // elements per material, first species held
+  const double* bounds;
+  const int* vmat;
+  const int* vbin;
+  const MatParams* mat;
+  __device__ __forceinline__ const R* of(int m, int sp) const {
+    return tab + m * mstride + (sp - sp0) * (kGrid * kQ);
+  }
+};
+
 // Grid interval and fraction of ln T (linear interpolation in ln E between nodes).
 template <class R>
 __device__ __forceinline__ void grid_pos(const Params& P, R lnT, int& i, R& f) {
@@ -148,10 +166,10 @@ __device__ __forceinline__ void grid_pos(const Params& P, R lnT, int& i, R& f) {
 
 // All kQ interpolated quantities of (material, species) at ln T.
 template <class R>
-__device__ __forceinline__ void lookup(const Params& P, int m, int sp, R lnT, R q[kQ], int& i) {
+__device__ __forceinline__ void lookup(const Params& P, const R* tb, R lnT, R q[kQ], int& i) {
   R f;
   grid_pos<R>(P, lnT, i, f);
-  const R* t = Px<R>::tab(P) + ((size_t)(m * 3 + sp) * kGrid + i) * kQ;
+  const R* t = tb + i * kQ;
 #pragma unroll
   for (int j = 0; j < kQ; ++j) {
     const R a = t[j], b = t[kQ + j];
@@ -176,8 +194,8 @@ __device__ __forceinline__ void thresholds(const MatParams& M, int sp, double T,
 // ln T' of the exact inverse of the piecewise-linear range table, starting the
 // search at interval i0 (T' <= T, so the answer is at or below it).
 template <class R>
-__device__ __forceinline__ R range_inverse(const Params& P, int m, int sp, R r, int i0) {
-  const R* t = Px<R>::tab(P) + (size_t)(m * 3 + sp) * kGrid * kQ + 3;
+__device__ __forceinline__ R range_inverse(const Params& P, const R* tb, R r, int i0) {
+  const R* t = tb + 3;
   if (r <= t[0]) return Px<R>::lnE0(P);
   if (r >= t[(kGrid - 1) * kQ]) return Px<R>::lnE0(P) + R(kGrid - 1) * Px<R>::dln(P);
   int i = i0 > kGrid - 2 ? kGrid - 2 : i0;
@@ -222,18 +240,18 @@ __device__ __forceinline__ int locate(const Params& P, double x, double y, doubl
 // (-1 = outside the world).  Slabs: z-planes to neighbours, walls |x|,|y| to the
 // outside (ties to the walls).  Shells: outer radius outward, inner radius inward,
 // end caps outside (ties inner, then caps).
-__device__ __forceinline__ double distance(const Params& P, int vol, double px, double py,
-                                           double pz, double dx, double dy, double dz,
-                                           int& next) {
+__device__ __forceinline__ double distance(const Params& P, const double* bounds, int vol,
+                                           double px, double py, double pz, double dx, double dy,
+                                           double dz, int& next) {
 #pragma clang fp contract(off)
   double s = HUGE_VAL;
   int nx = -1;
   if (P.gkind == EMS_GEOM_SLABS) {
     if (dz > 0.0) {
-      s = (P.bounds[vol + 1] - pz) / dz;
+      s = (bounds[vol + 1] - pz) / dz;
       nx = vol + 1 < P.nvol ? vol + 1 : -1;
     } else if (dz < 0.0) {
-      s = (P.bounds[vol] - pz) / dz;
+      s = (bounds[vol] - pz) / dz;
       nx = vol > 0 ? vol - 1 : -1;
     }
     if (dx != 0.0) {
@@ -255,14 +273,14 @@ __device__ __forceinline__ double distance(const Params& P, int vol, double px, 
     const double b = px * dx + py * dy;
     const double r2 = px * px + py * py;
     if (a > 0.0) {
-      const double Ro = P.bounds[vol + 1];
+      const double Ro = bounds[vol + 1];
       const double c = r2 - Ro * Ro;
       const double D = fmax(b * b - a * c, 0.0);
       const double sq = sqrt(D);
       s = (b <= 0.0) ? (sq - b) / a : -c / (b + sq);
       nx = vol + 1 < P.nvol ? vol + 1 : -1;
       if (vol > 0 && b < 0.0) {
-        const double Ri = P.bounds[vol];
+        const double Ri = bounds[vol];
         const double ci = r2 - Ri * Ri;
         const double Di = b * b - a * ci;
         if (Di >= 0.0) {
@@ -371,7 +389,8 @@ __device__ __forceinline__ void rk4(double kappa, double h, double rx, double ry
 // with step-doubling error control, the boundary searched on each substep's chord
 // and accepted once the chord's sagitta is within tolerance.  Returns 0 at s_max,
 // 1 at a boundary (next set), 2 for a looper (vacuum path cap or substep cap).
-__device__ __forceinline__ int field_move(const Params& P, int vol, double kappa, double s_max,
+__device__ __forceinline__ int field_move(const Params& P, const double* bounds, int vol,
+                                          double kappa, double s_max,
                                           bool vacuum, double& x, double& y, double& z,
                                           double& u, double& v, double& w, double& s_out,
                                           int& next) {
@@ -400,7 +419,7 @@ __device__ __forceinline__ int field_move(const Params& P, int vol, double kappa
       cx /= L;
       cy /= L;
       cz /= L;
-      sb = distance(P, vol, x, y, z, cx, cy, cz, nx);
+      sb = distance(P, bounds, vol, x, y, z, cx, cy, cz, nx);
     }
     if (sb < L) {
       const double qx = mx - x, qy = my - y, qz = mz - z;
@@ -541,12 +560,13 @@ struct Moved {
 // step ends in an interaction (or a positron that stops) is sent to a queue with
 // its step count not yet incremented; every other survivor's count is incremented.
 template <class R, bool FIELD>
-__device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
+__device__ __forceinline__ void transport(const Params& P, const View<R>& V, Track& t, Moved& o) {
   const double INF = HUGE_VAL;
   const int sp = t.sp;
-  const int m = P.vmat[t.vol];
+  const int m = V.vmat[t.vol];
   const int mm = m < 0 ? 0 : m;
-  const bool matter = m >= 0 && !P.mat[mm].vacuum;
+  const bool matter = m >= 0 && !V.mat[mm].vacuum;
+  const R* tb = V.of(mm, sp);
   const bool charged = sp != EMS_GAMMA;
   Stream st;
   st.init(t.k0, t.k1, t.k2, t.nstep, P.seed);
@@ -558,9 +578,9 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   int i0 = 0;
   R sigtot = R(0);
   if (matter) {
-    lookup<R>(P, mm, sp, lnT, q, i0);
+    lookup<R>(P, tb, lnT, q, i0);
     bool on0, on1, on2;
-    thresholds(P.mat[mm], sp, t.T, on0, on1, on2);
+    thresholds(V.mat[mm], sp, t.T, on0, on1, on2);
     sigtot = (on0 ? q[0] : R(0)) + (on1 ? q[1] : R(0)) + (on2 ? q[2] : R(0));
   }
   const double s_phys = sigtot > R(0) ? (double)Px<R>::dv((R)t.nlam, sigtot) : INF;
@@ -570,7 +590,7 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   R R0 = R(0), dres = R(0);
   if (lossy) {
     R0 = q[3];
-    dres = R0 - Px<R>::rtrk(P.mat[mm], sp);
+    dres = R0 - Px<R>::rtrk(V.mat[mm], sp);
     const R rf = Px<R>::rfin(P);
     R sc = dres <= rf ? dres : fmax(Px<R>::alpha(P) * dres, rf);
     s_cont = sc < R(0) ? 0.0 : (double)sc;
@@ -582,11 +602,11 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
   if (FIELD && charged) {  // curved path up to the physics limit; a boundary met first wins
     const double p = sqrt(t.T * (t.T + 2.0 * kMe));
     const double kappa = 2.99792458 * (sp == EMS_ELECTRON ? -1.0 : 1.0) * P.bz / p;
-    const int res = field_move(P, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
+    const int res = field_move(P, V.bounds, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
                                t.u, t.v, t.w, s, next);
     lim = res == 1 ? 0 : (res == 2 ? 3 : (s_phys <= s_cont ? 1 : 2));
   } else {
-    const double s_geo = distance(P, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
+    const double s_geo = distance(P, V.bounds, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
     if (s_geo <= s_phys && s_geo <= s_cont) {
       lim = 0;
       s = s_geo;
@@ -614,7 +634,7 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
       T1 = 0.0;
       stopped = true;
     } else {
-      lnT1 = range_inverse<R>(P, mm, sp, R0 - (R)s, i0);
+      lnT1 = range_inverse<R>(P, tb, R0 - (R)s, i0);
       T1 = (double)Px<R>::ex(lnT1);
       if (T1 > T0) {
         T1 = T0;
@@ -647,9 +667,9 @@ __device__ __forceinline__ void transport(const Params& P, Track& t, Moved& o) {
     t.nlam = -1.0;
     R q2[kQ];
     int i1;
-    lookup<R>(P, mm, sp, lnT1, q2, i1);
+    lookup<R>(P, tb, lnT1, q2, i1);
     bool on0, on1, on2;
-    thresholds(P.mat[mm], sp, T1, on0, on1, on2);
+    thresholds(V.mat[mm], sp, T1, on0, on1, on2);
     const R x0 = on0 ? q2[0] : R(0), x1 = on1 ? q2[1] : R(0), x2 = on2 ? q2[2] : R(0);
     const R tot = x0 + x1 + x2;
     if (tot > R(0)) {
@@ -905,13 +925,76 @@ __device__ __forceinline__ void count_done(const Params& P, uint32_t e, int delt
   }
 }
 
+// Bytes of the per-block LDS copy of the run data: the tables of the larger
+// species class (electron and positron) of every material, then the volume
+// bounds, the volume -> material map and the volume -> tally-bin map.
+__host__ __device__ __forceinline__ uint32_t stage_tab_bytes(int n_mats, uint32_t rsize) {
+  return (uint32_t)n_mats * 2u * kGrid * kQ * rsize;
+}
+__host__ __device__ __forceinline__ uint32_t align16(uint32_t b) { return (b + 15u) & ~15u; }
+__host__ __device__ __forceinline__ uint32_t stage_bytes(int n_mats, int nvol, uint32_t rsize) {
+  return stage_tab_bytes(n_mats, rsize) + align16(8u * (uint32_t)(nvol + 1)) +
+         2u * align16(4u * (uint32_t)nvol);
+}
+
+extern __shared__ uint4 ems_stage[];  // dynamic LDS of the step kernels
+
+// Build the block's view of the run data.  Material parameters are always copied
+// to LDS; with STAGED the tables of the block's species class (charged: electron
+// and positron) and the geometry maps are too.  Ends with a block barrier.
+template <class R, bool STAGED>
+__device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_class,
+                                              MatParams* sh_mat) {
+  View<R> V;
+  if (threadIdx.x < (unsigned)P.n_mats) sh_mat[threadIdx.x] = P.mat[threadIdx.x];
+  V.mat = sh_mat;
+  if (STAGED) {
+    unsigned char* base = reinterpret_cast<unsigned char*>(ems_stage);
+    const int sp0 = charged_class ? 1 : 0;
+    const uint32_t per = (charged_class ? 2u : 1u) * kGrid * kQ;  // elements per material
+    const uint32_t per16 = per * (uint32_t)sizeof(R) / 16u;
+    const uint4* g = reinterpret_cast<const uint4*>(Px<R>::tab(P));
+    uint4* l = ems_stage;
+    for (int m = 0; m < P.n_mats; ++m) {
+      const uint4* src = g + (size_t)(m * 3 + sp0) * (kGrid * kQ * sizeof(R) / 16u);
+      for (uint32_t j = threadIdx.x; j < per16; j += kBlock) l[m * per16 + j] = src[j];
+    }
+    const uint32_t ob = stage_tab_bytes(P.n_mats, sizeof(R));
+    const uint32_t om = ob + align16(8u * (uint32_t)(P.nvol + 1));
+    const uint32_t oi = om + align16(4u * (uint32_t)P.nvol);
+    double* bnd = reinterpret_cast<double*>(base + ob);
+    int* vm = reinterpret_cast<int*>(base + om);
+    int* vb = reinterpret_cast<int*>(base + oi);
+    for (int j = threadIdx.x; j <= P.nvol; j += kBlock) bnd[j] = P.bounds[j];
+    for (int j = threadIdx.x; j < P.nvol; j += kBlock) {
+      vm[j] = P.vmat[j];
+      vb[j] = P.vbin[j];
+    }
+    V.tab = reinterpret_cast<const R*>(base);
+    V.mstride = (int)per;
+    V.sp0 = sp0;
+    V.bounds = bnd;
+    V.vmat = vm;
+    V.vbin = vb;
+  } else {
+    V.tab = Px<R>::tab(P);
+    V.mstride = 3 * kGrid * kQ;
+    V.sp0 = 0;
+    V.bounds = P.bounds;
+    V.vmat = P.vmat;
+    V.vbin = P.vbin;
+  }
+  __syncthreads();
+  return V;
+}
+
 // One iteration, part 1, for chunk c of kBlock tracks: chunks [0, nbG) of the
 // photon pool, then the charged pool (so every wavefront holds one species class).
 // In each pool the first k tracks are stepped and the rest copied unchanged
 // (deferred for lack of output room).  Survivors go to the output pool of their
 // class, tracks that interact to their process queue; both are reserved once per
 // block.
-template <class R, bool FIELD>
+template <class R, bool FIELD, bool STAGED>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
                                                 uint32_t c, uint32_t nG, uint32_t kG, uint32_t nC,
@@ -926,17 +1009,14 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   Moved o{};
   o.process = -1;
   o.dest = -2;
-  bool stepped = false, usable = valid, vol_out = false;
+  bool stepped = false, vol_out = false;
   uint32_t vol = 0;
+  // every field of the state is loaded at once (one round trip), checked after
   if (valid) {
     const uint32_t meta = S.meta[io + i];
     t.sp = (int)(meta & 3u);
     vol = meta >> 2;
     t.evt = S.evt[io + i];
-    // a state that names no species, volume or event slot of this run is dropped
-    usable = t.sp <= 2 && (vol == kVolOut || vol < (uint32_t)P.nvol) && t.evt < P.max_events;
-  }
-  if (usable) {
     t.x = S.x[io + i];
     t.y = S.y[io + i];
     t.z = S.z[io + i];
@@ -950,6 +1030,13 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     t.k2 = S.k2[io + i];
     t.nstep = S.nstep[io + i];
     t.src = rec ? S.src[io + i] : 0u;
+  }
+  __shared__ MatParams sh_mat[kMaxMat];
+  const View<R> V = stage_view<R, STAGED>(P, cblk, sh_mat);
+  // a state that names no species, volume or event slot of this run is dropped
+  const bool usable =
+      valid && t.sp <= 2 && (vol == kVolOut || vol < (uint32_t)P.nvol) && t.evt < P.max_events;
+  if (usable) {
     if (vol == kVolOut) {  // primary born outside the world: escapes with no step
       vol_out = true;
       t.vol = 0;
@@ -958,7 +1045,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     } else {
       t.vol = (int)vol;
       if (i < k) {
-        transport<R, FIELD>(P, t, o);
+        transport<R, FIELD>(P, V, t, o);
         stepped = true;
       } else {
         o.dest = -1;  // deferred: copied unchanged
@@ -1044,7 +1131,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   // ---- tallies of the event slot (deposits are scored in the pre-step volume)
   const uint32_t e = t.evt;
   const double sc = P.scale[e];
-  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + P.vbin[vol_out ? 0 : (int)vol]],
+  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + V.vbin[vol_out ? 0 : (int)vol]],
                              fixed_point(o.dep, sc));
   if (o.esc > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 0], fixed_point(o.esc, sc));
   if (o.killed > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(o.killed, sc));
@@ -1072,7 +1159,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // Part 1 as a kernel, one chunk per block: pool sizes come from the admission
 // cursors and the deferral bound k = min(n, (cap - n)/2) is taken on the device, so
 // the host launches an upper bound of blocks and the surplus exits at once.
-template <class R, bool FIELD>
+template <class R, bool FIELD, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t N, int cur,
                                                       IQueue Q, ems_step_record* rec,
                                                       uint32_t cap) {
@@ -1092,7 +1179,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t
     if (k == 0) atomicAdd(&st[kSStall], 1ull);
   }
   if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
-  transport_chunk<R, FIELD>(P, S, N, cur, Q, rec, blockIdx.x, nG, kG, nC, kC, nbG);
+  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, kG, nC, kC, nbG);
 }
 
 // Wave-aggregated append of one output stream (parent or secondary j) into the
@@ -1431,14 +1518,30 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   const dim3 b(kBlock);
   const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
   const bool field = P.bz != 0.0;
-  if (mixed && field)
-    hipLaunchKernelGGL((k_transport<float, true>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
-  else if (mixed)
-    hipLaunchKernelGGL((k_transport<float, false>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
-  else if (field)
-    hipLaunchKernelGGL((k_transport<double, true>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
-  else
-    hipLaunchKernelGGL((k_transport<double, false>), gT, b, 0, s, P, S, N, cur, Q, rec, cap);
+  // the run data is staged in LDS when it fits the per-block budget
+  const uint32_t lds = stage_bytes(P.n_mats, P.nvol, mixed ? sizeof(float) : sizeof(double));
+  const bool staged = lds <= kStageMaxBytes;
+  const uint32_t sh = staged ? lds : 0u;
+#define EMS_LAUNCH_T(R, F, ST) \
+  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec, cap)
+  if (mixed) {
+    if (field) {
+      if (staged) EMS_LAUNCH_T(float, true, true);
+      else EMS_LAUNCH_T(float, true, false);
+    } else {
+      if (staged) EMS_LAUNCH_T(float, false, true);
+      else EMS_LAUNCH_T(float, false, false);
+    }
+  } else {
+    if (field) {
+      if (staged) EMS_LAUNCH_T(double, true, true);
+      else EMS_LAUNCH_T(double, true, false);
+    } else {
+      if (staged) EMS_LAUNCH_T(double, false, true);
+      else EMS_LAUNCH_T(double, false, false);
+    }
+  }
+#undef EMS_LAUNCH_T
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec);
