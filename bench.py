@@ -70,6 +70,26 @@ def cpu_baseline(n_events, energy, seed, budget_s=12.0):
                        f"{wall:.1f} s wall, {len(jobs)} processes)")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_calorimeter_fp64_traffic.json")
+
+
+def measured_traffic(args):
+    """HBM bytes per step iteration from the committed FETCH_SIZE / WRITE_SIZE counters
+    of the default FP64 calorimeter workload, or None when they do not apply (another
+    workload or precision, or kernel source changed since they were taken)."""
+    import hashlib
+    if args.precision != "fp64" or args.events != 100_000 or args.energy != 1000.0:
+        return None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, t["kernel_source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return float(t["bytes_per_iteration"]) if sha == t["kernel_source_sha256"] else None
+
+
 def run_transport(ems, wl, n_events, args, precision, log_name):
     """Transport the whole batch args.warmup + args.steps times; returns the timed totals."""
     import torch
@@ -122,7 +142,7 @@ def run_serving(ems, args, precision):
     wl = W.serving(n_events=args.serve_events, rate_hz=args.serve_rate)
     ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
                       max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
-                      seed=wl.seed, precision=precision, energy_budget=args.budget,
+                      seed=wl.seed, precision=precision, energy_budget=args.serve_budget,
                       iterations_per_sync=min(args.per_sync, args.serve_iters))
     ctx.setup(wl.materials, wl.options, wl.geometry)
     res = serve(ctx, wl.events, iterations=args.serve_iters, time_limit=300.0)
@@ -145,12 +165,14 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool", type=int, default=1 << 24)
     ap.add_argument("--budget", type=float, default=2.5e7, help="energy in flight, MeV")
-    ap.add_argument("--per-sync", type=int, default=8,
+    ap.add_argument("--per-sync", type=int, default=2,
                     help="step iterations launched back to back between host synchronisations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-events", type=int, default=200)
+    ap.add_argument("--serve-events", type=int, default=1000)
+    ap.add_argument("--serve-budget", type=float, default=5e7,
+                    help="energy in flight of the serving loop, MeV")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
     ap.add_argument("--serve-iters", type=int, default=32,
                     help="step iterations per transport call of the serving loop")
@@ -205,7 +227,9 @@ def main():
                    "peak_tracks_in_flight": r["peak"], "track_steps": r["steps"],
                    "ledger_max_rel_error": r["ledger_max"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
+                     "traffic_unit": "bytes per iteration",
+                     "algorithmic_bytes_per_iteration": bytes_alg / max(st.launches, 1),
                      "kernel": "step kernels (k_transport + k_interact)",
                      "launches": st.launches,
                      "avg_iteration_ms": st.kernel_ms / max(st.launches, 1),

@@ -16,13 +16,15 @@ constexpr int kGrid = 200;            // nodes of the log energy grid, 1 keV .. 
 constexpr int kQ = 4;                 // quantities per (material, species, node)
 constexpr int kMaxMat = 8;
 constexpr int kLedger = 4;            // escaped (fixed point), killed (fixed point), pairs, annihilations
-constexpr uint32_t kVolOut = 0x3FFFFFFFu;  // meta volume of a primary that starts outside
+constexpr uint32_t kVolOut = 0x3FFFFFFu;  // meta volume of a primary that starts outside
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
 constexpr int kBlock = 512;
 constexpr uint32_t kStageMaxBytes = 64u * 1024u;  // per-block LDS budget of the staged run data
 
-// Tracks in flight, SoA.  meta = species (bits 0-1) | volume << 2.  Photons and
+// Tracks in flight, SoA.  meta = species (bits 0-1) | pending (bit 2) | queue of
+// the pending interaction (bits 3-5) | volume << 6; a pending track ended its last
+// step in an interaction that was put off for lack of output room.  Photons and
 // charged tracks live in separate pools so that a wavefront steps one species
 // class, each double-buffered.  A Pool passed to the step kernels is the set of
 // all four buffers: for every field, buffer (class c, parity b) occupies elements
@@ -51,20 +53,32 @@ struct IQueue {
 // Device counters of one iteration.  Each counter line is 256 bytes apart so that
 // concurrent atomics on different counters meet different cache lines and memory
 // channels; two 32-bit counters share one 64-bit word (low, high) and are
-// advanced together by one 64-bit atomic.
+// advanced together by one 64-bit atomic.  Statistics are spread over kStatCopies
+// lines (a block adds to copy blockIdx % kStatCopies) so that no single address
+// takes one atomic per block.
 enum CounterLine {
-  kLOut = 0,      // output pools: photons (low), charged (high)
+  kLOut = 0,      // output pools, survivors of the transport kernel: photons (low), charged (high)
   kLQueue = 1,    // lines 1..4: queue sizes (2i low, 2i+1 high)
   kLDone = 5,     // finished-event list length (low)
-  kLAdmit = 6,    // admission cursors: photons (low), charged (high)
-  kLPosSteps = 7, // positron track-steps since the interval began
-  kLStats = 8,    // interval statistics, words kS*
-  kNumLines = 9
+  kLAdmit = 6,    // admission cursors = pool sizes: photons (low), charged (high)
+  kLOutI = 7,     // output pools, tracks written by the interaction kernel (low, high)
+  kLStats = 8,    // lines 8 .. 8 + kStatCopies - 1: interval statistics, words kS*
 };
-// words of the statistics line (sums over the iterations of a sync interval)
+constexpr int kStatCopies = 16;
+constexpr int kNumLines = kLStats + kStatCopies;
+// words of a statistics line (sums over the iterations of a sync interval)
 enum StatWord {
-  kSIn = 0, kSStepped = 1, kSStepG = 2, kSStepC = 3, kSOut = 4, kSQueued = 5, kSStall = 6,
-  kSBusy = 7, kSPeak = 8
+  kSIn = 0,        // tracks in the pool at the start of an iteration
+  kSStepG = 1,     // photon track-steps
+  kSStepC = 2,     // charged track-steps
+  kSStepPos = 3,   // positron track-steps
+  kSPending = 4,   // pending tracks sent back to their interaction queue
+  kSDeferred = 5,  // interactions put off (written back as pending tracks)
+  kSOut = 6,       // tracks in the output pools
+  kSQueued = 7,    // tracks queued for an interaction
+  kSStall = 8,     // iterations in which no interaction could be done for lack of room
+  kSBusy = 9,      // iterations with a non-empty pool
+  kSPeak = 10      // largest pool
 };
 constexpr int kLineWords = 32;  // 64-bit words per line
 

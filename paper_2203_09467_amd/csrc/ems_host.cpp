@@ -231,7 +231,8 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
 
 bool config_ok(const ems_config* c) {
   return c && c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && c->max_events >= 1 &&
-         c->max_bins >= 1 && c->queue_capacity >= 1 && c->iterations_per_sync <= kMaxPerSync &&
+         c->max_bins >= 1 && (uint64_t)c->max_events * c->max_bins < (1ull << 29) &&
+         c->queue_capacity >= 1 && c->iterations_per_sync <= kMaxPerSync &&
          (c->precision == EMS_FP64 || c->precision == EMS_MIXED);
 }
 
@@ -495,14 +496,20 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
 }
 
 // One sync interval: up to `iters` iterations enqueued back to back (admission
-// only at its start), then one readback of the counters.  Pool sizes, the
-// deferral bound and the queue sizes stay on the device between iterations.
+// only at its start), then one readback of the counters.  Pool sizes and queue
+// sizes stay on the device between iterations.  The pool is kept within `bound`
+// tracks by the interaction kernel (interactions that would not fit are put off),
+// so every launch covers at most `bound` tracks: twice the pool at the start of
+// the interval plus a margin, or the whole capacity when full_room is set.
 struct IntervalOut {
   uint64_t stepped = 0, deferred = 0, busy = 0, peak = 0;
 };
 
+constexpr uint32_t kBoundMargin = 65536;
+constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
+
 ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
-                        bool admit_first, IntervalOut* io) {
+                        bool admit_first, bool full_room, IntervalOut* io) {
   HIP_OK(launch_iter_begin(x->ctr, true, x->nG, x->nC, s));
   if (admit_first) {
     uint32_t m = 0;
@@ -516,34 +523,37 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   }
   const uint32_t cap = x->cfg.pool_capacity;
   const bool mixed = x->cfg.precision == EMS_MIXED;
-  // every stepped track leaves at most three, and the pool never exceeds its capacity
-  uint64_t bound = (uint64_t)x->nG + x->nC;
+  const uint64_t n0 = (uint64_t)x->nG + x->nC;
+  const uint32_t bound =
+      full_room ? cap : (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(n0, 2 * n0 + kBoundMargin));
   for (int j = 0; j < iters; ++j) {
-    if (j > 0) {
-      HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
-      bound = std::min<uint64_t>(cap, 3 * bound);
-    }
+    if (j > 0) HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
     if (x->ev[2 * j]) HIP_OK(hipEventRecord(x->ev[2 * j], s));
-    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, (uint32_t)bound, mixed, rec, s));
+    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, mixed, rec, s));
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
     x->cur = 1 - x->cur;
   }
+  const uint32_t pre = std::min<uint32_t>(x->cfg.max_events, kDonePrefetch);
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, pre * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const unsigned long long* L = x->h_ctr;
-  const unsigned long long* S = L + kLStats * kLineWords;
-  const uint32_t outG = (uint32_t)L[kLOut * kLineWords], outC = (uint32_t)(L[kLOut * kLineWords] >> 32);
+  unsigned long long S[kLineWords] = {};
+  for (int c = 0; c < kStatCopies; ++c)
+    for (int w = 0; w < kLineWords; ++w) S[w] += L[(kLStats + c) * kLineWords + w];
+  S[kSPeak] = L[kLStats * kLineWords + kSPeak];
+  const unsigned long long out = L[kLOut * kLineWords] + L[kLOutI * kLineWords];
+  const uint32_t outG = (uint32_t)(out & 0xFFFFFFFFull), outC = (uint32_t)(out >> 32);
   const uint32_t n_done = std::min((uint32_t)L[kLDone * kLineWords], x->cfg.max_events);
-  const uint64_t pos_steps = L[kLPosSteps * kLineWords];
   uint64_t queued_last = 0;
   for (int l = 0; l < 4; ++l) {
     const unsigned long long v = L[(kLQueue + l) * kLineWords];
     queued_last += (v & 0xFFFFFFFFull) + (v >> 32);
   }
   x->run_steps[EMS_GAMMA] += S[kSStepG];
-  x->run_steps[EMS_POSITRON] += pos_steps;
-  x->run_steps[EMS_ELECTRON] += S[kSStepC] - pos_steps;
+  x->run_steps[EMS_POSITRON] += S[kSStepPos];
+  x->run_steps[EMS_ELECTRON] += S[kSStepC] - S[kSStepPos];
   x->stats.launches += S[kSBusy];
   x->stats.tracks_in += S[kSIn];
   x->stats.tracks_out += S[kSOut] + outG + outC;
@@ -556,8 +566,10 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
     }
   }
   if (n_done) {
-    HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, n_done * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    if (n_done > pre) {
+      HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, n_done * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+    }
     for (uint32_t j = 0; j < n_done; ++j) {
       const uint32_t sl = x->h_done[j];
       if (sl < x->slot_state.size() && x->slot_state[sl] == 1) {
@@ -569,8 +581,8 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   }
   x->nG = outG;
   x->nC = outC;
-  io->stepped += S[kSStepped];
-  io->deferred += S[kSIn] - S[kSStepped];
+  io->stepped += S[kSStepG] + S[kSStepC];
+  io->deferred += S[kSDeferred];
   io->busy += S[kSBusy];
   io->peak = std::max<uint64_t>(io->peak, S[kSPeak]);
   if (S[kSStall]) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
@@ -598,7 +610,7 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
     if (x->nG + x->nC == 0 && x->pending.empty()) break;
     int k = per_sync;
     if (max_iterations >= 0) k = (int)std::min<uint64_t>((uint64_t)k, (uint64_t)max_iterations - it);
-    const ems_status st = run_interval(x, s, nullptr, k, true, &io);
+    const ems_status st = run_interval(x, s, nullptr, k, true, false, &io);
     if (st != EMS_OK) return st;
     it += k;
   }
@@ -699,7 +711,7 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   x->nG = (uint32_t)x->h_ctr[kLAdmit * kLineWords];
   x->nC = (uint32_t)(x->h_ctr[kLAdmit * kLineWords] >> 32);
   IntervalOut io;
-  ems_status st = run_interval(x, s, rec, 1, false, &io);
+  ems_status st = run_interval(x, s, rec, 1, false, true, &io);
   if (st != EMS_OK) return st;
   HIP_OK(launch_pool_dump(x->pool[0][x->cur], *out, x->nG, 0, s));
   HIP_OK(launch_pool_dump(x->pool[1][x->cur], *out, x->nC, x->nG, s));

@@ -880,10 +880,22 @@ __device__ __forceinline__ unsigned long long* ctr_line(const Params& P, int l) 
 __device__ __forceinline__ uint32_t lo32(unsigned long long v) { return (uint32_t)(v & 0xFFFFFFFFull); }
 __device__ __forceinline__ uint32_t hi32(unsigned long long v) { return (uint32_t)(v >> 32); }
 
+// statistics line of this block
+__device__ __forceinline__ unsigned long long* stat_line(const Params& P) {
+  return ctr_line(P, kLStats + (int)(blockIdx.x % kStatCopies));
+}
+
 // size of interaction queue q this iteration
 __device__ __forceinline__ uint32_t queue_size(const Params& P, int q) {
   const unsigned long long v = *ctr_line(P, kLQueue + (q >> 1));
   return (q & 1) ? hi32(v) : lo32(v);
+}
+
+__device__ __forceinline__ uint32_t make_meta(int sp, uint32_t vol) {
+  return (uint32_t)sp | (vol << 6);
+}
+__device__ __forceinline__ uint32_t make_pending_meta(int sp, int q, uint32_t vol) {
+  return (uint32_t)sp | 4u | ((uint32_t)q << 3) | (vol << 6);
 }
 
 __device__ __forceinline__ void write_track(const Pool& p, size_t j, int sp, int vol, double x,
@@ -903,7 +915,7 @@ __device__ __forceinline__ void write_track(const Pool& p, size_t j, int sp, int
   p.k2[j] = k2;
   p.evt[j] = evt;
   p.nstep[j] = nstep;
-  p.meta[j] = (uint32_t)sp | ((uint32_t)vol << 2);
+  p.meta[j] = make_meta(sp, (uint32_t)vol);
 }
 
 // Element offset of pool buffer (class, parity) in the pool set: for every field
@@ -916,12 +928,76 @@ __device__ __forceinline__ unsigned long long fixed_point(double e, double scale
   return (unsigned long long)llrint(e * scale);
 }
 
-__device__ __forceinline__ void count_done(const Params& P, uint32_t e, int delta) {
-  if (delta == 0) return;
-  const int old = atomicAdd(&P.alive[e], delta);
-  if (old + delta == 0) {
-    const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
-    if (k < P.max_events) P.done[k] = e;
+// Per-event scores of one block -- tally bins, ledger words, escape-spectrum bins
+// and changes of the events' alive counts -- are summed in an LDS hash table and
+// added to global memory once per distinct key.  The sums are integers (fixed-point
+// energies, counts), so grouping them changes no result.  Key = tag << 29 | index.
+constexpr int kAggSlots = 1024;
+constexpr int kAggProbes = 32;
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+enum AggTag : uint32_t {
+  kTagTally = 0,   // index = slot * nbins + bin
+  kTagLedger = 1,  // tags 1..4: ledger word tag - 1, index = slot
+  kTagAlive = 5,   // index = slot, value = change of the alive count (two's complement)
+  kTagEsc = 6      // index = species * kGrid + bin of the escape spectrum
+};
+struct Agg {
+  uint32_t key[kAggSlots];
+  unsigned long long val[kAggSlots];
+};
+
+__device__ __forceinline__ uint32_t agg_key(uint32_t tag, uint32_t index) { return (tag << 29) | index; }
+
+// Add one aggregated score to global memory.  An alive count that reaches zero
+// puts its event slot on the finished list.
+__device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsigned long long v) {
+  const uint32_t tag = key >> 29, idx = key & 0x1FFFFFFFu;
+  if (tag == kTagTally) {
+    atomicAdd(&P.tally[idx], v);
+  } else if (tag < kTagAlive) {
+    atomicAdd(&P.ledger[(size_t)idx * kLedger + (tag - kTagLedger)], v);
+  } else if (tag == kTagAlive) {
+    const int d = (int)(long long)v;
+    const int old = atomicAdd(&P.alive[idx], d);
+    if (old + d == 0) {
+      const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
+      if (k < P.max_events) P.done[k] = idx;
+    }
+  } else {
+    atomicAdd(&P.esc_hist[idx], v);
+  }
+}
+
+__device__ __forceinline__ void agg_init(Agg& A) {
+  for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+    A.key[j] = kAggEmpty;
+    A.val[j] = 0ull;
+  }
+}
+
+// Insert with linear probing (bounded: a crowded table falls back to a global add).
+__device__ __forceinline__ void agg_add(const Params& P, Agg& A, uint32_t key,
+                                        unsigned long long v) {
+  uint32_t h = (key * 0x9E3779B1u) >> 22;
+#pragma nounroll
+  for (int p = 0; p < kAggProbes; ++p) {
+    const uint32_t prev = atomicCAS(&A.key[h], kAggEmpty, key);
+    if (prev == kAggEmpty || prev == key) {
+      atomicAdd(&A.val[h], v);
+      return;
+    }
+    h = (h + 1u) & (kAggSlots - 1);
+  }
+  agg_global(P, key, v);
+}
+
+// One global add per distinct key; called after a block barrier that follows every
+// lane's inserts.
+__device__ __forceinline__ void agg_flush(const Params& P, Agg& A) {
+  for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+    const uint32_t key = A.key[j];
+    const unsigned long long v = A.val[j];
+    if (key != kAggEmpty && v != 0ull) agg_global(P, key, v);
   }
 }
 
@@ -997,11 +1073,11 @@ __device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_clas
 template <class R, bool FIELD, bool STAGED>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
-                                                uint32_t c, uint32_t nG, uint32_t kG, uint32_t nC,
-                                                uint32_t kC, uint32_t nbG) {
+                                                uint32_t c, uint32_t nG, uint32_t nC,
+                                                uint32_t nbG) {
   const bool cblk = c >= nbG;
   const size_t io = buf_off(cblk, cur, N), oo = buf_off(cblk, 1 - cur, N);
-  const uint32_t n = cblk ? nC : nG, k = cblk ? kC : kG;
+  const uint32_t n = cblk ? nC : nG;
   const uint32_t i = (c - (cblk ? nbG : 0u)) * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = i < n;
@@ -1009,13 +1085,16 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   Moved o{};
   o.process = -1;
   o.dest = -2;
-  bool stepped = false, vol_out = false;
+  bool stepped = false, vol_out = false, pending = false;
   uint32_t vol = 0;
+  int pq = 0;
   // every field of the state is loaded at once (one round trip), checked after
   if (valid) {
     const uint32_t meta = S.meta[io + i];
     t.sp = (int)(meta & 3u);
-    vol = meta >> 2;
+    pending = (meta & 4u) != 0u;
+    pq = (int)((meta >> 3) & 7u);
+    vol = meta >> 6;
     t.evt = S.evt[io + i];
     t.x = S.x[io + i];
     t.y = S.y[io + i];
@@ -1032,6 +1111,8 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     t.src = rec ? S.src[io + i] : 0u;
   }
   __shared__ MatParams sh_mat[kMaxMat];
+  __shared__ Agg sh_agg;
+  agg_init(sh_agg);
   const View<R> V = stage_view<R, STAGED>(P, cblk, sh_mat);
   // a state that names no species, volume or event slot of this run is dropped
   const bool usable =
@@ -1044,18 +1125,47 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       o.escaped = 1;
     } else {
       t.vol = (int)vol;
-      if (i < k) {
+      if (pending) {
+        o.dest = pq;  // its interaction, put off last iteration, is done now
+      } else {
         transport<R, FIELD>(P, V, t, o);
         stepped = true;
-      } else {
-        o.dest = -1;  // deferred: copied unchanged
       }
     }
   }
 
+  // ---- scores of the event slot (deposits are scored in the pre-step volume)
+  if (usable && (stepped || vol_out)) {
+    const uint32_t e = t.evt;
+    const double sc = P.scale[e];
+    if (o.dep > 0.0)
+      agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)V.vbin[vol_out ? 0 : (int)vol]),
+              fixed_point(o.dep, sc));
+    if (o.esc > 0.0) agg_add(P, sh_agg, agg_key(kTagLedger + 0, e), fixed_point(o.esc, sc));
+    if (o.killed > 0.0) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(o.killed, sc));
+    if (o.escaped) {
+      const double tt = (log(o.esc) - P.lnE0) * P.inv_dlnE;
+      const int b = !(tt > 0.0) ? 0 : (tt >= (double)(kGrid - 1) ? kGrid - 1 : (int)tt);
+      agg_add(P, sh_agg, agg_key(kTagEsc, (uint32_t)(t.sp * kGrid + b)), 1ull);
+    }
+    if (o.dest == -2) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
+    if (rec && stepped) {
+      ems_step_record& r = rec[t.src];
+      r.dep = o.dep;
+      r.esc = o.esc;
+      r.killed = o.killed;
+      r.step_len = o.step_len;
+      r.limiter = o.limiter;
+      r.process = o.process;
+      r.n_pair = 0;
+      r.n_annih = 0;
+      r.n_out = o.dest == -1 ? 1 : 0;
+      r.escaped = o.escaped;
+    }
+  }
   // ---- block-level reservation: stream 0 survivors (output pool of this class),
   // 1..8 process queues, 9 positron track-steps; one 64-bit atomic per counter line
-  constexpr int kW = kBlock / 64, kS = 10;
+  constexpr int kW = kBlock / 64, kS = 12;
   __shared__ uint32_t sh_cnt[kW][kS];
   __shared__ uint32_t sh_base[kS];
   const int wave = threadIdx.x >> 6;
@@ -1064,12 +1174,15 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) mq[q] = __ballot(o.dest == q);
   const uint64_t mpos = __ballot(stepped && t.sp == EMS_POSITRON);
+  const uint64_t mstep = __ballot(stepped), mpend = __ballot(pending && usable);
   __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
     sh_cnt[wave][0] = (uint32_t)__popcll(mS);
 #pragma unroll
     for (int q = 0; q < kNumQueues; ++q) sh_cnt[wave][1 + q] = (uint32_t)__popcll(mq[q]);
-    sh_cnt[wave][9] = (uint32_t)__popcll(mpos);
+    sh_cnt[wave][9] = (uint32_t)__popcll(mstep);
+    sh_cnt[wave][10] = (uint32_t)__popcll(mpos);
+    sh_cnt[wave][11] = (uint32_t)__popcll(mpend);
   }
   __syncthreads();
   if (threadIdx.x < 6) {
@@ -1093,11 +1206,16 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       sh_base[s0] = lo32(old);
       sh_base[s0 + 1] = hi32(old);
     } else {
-      const uint32_t a = tot(9);
-      if (a) atomicAdd(ctr_line(P, kLPosSteps), (unsigned long long)a);
+      // block statistics: photon or charged steps, positron steps, pending tracks
+      const uint32_t st = tot(9), pos = tot(10), pend = tot(11);
+      unsigned long long* L = stat_line(P);
+      if (st) atomicAdd(&L[cblk ? kSStepC : kSStepG], (unsigned long long)st);
+      if (pos) atomicAdd(&L[kSStepPos], (unsigned long long)pos);
+      if (pend) atomicAdd(&L[kSPending], (unsigned long long)pend);
     }
   }
-  __syncthreads();
+  __syncthreads();  // also completes every lane's score inserts
+  agg_flush(P, sh_agg);
   if (o.dest == -1) {
     uint32_t j = sh_base[0] + lanes_below(mS, lane);
     for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][0];
@@ -1124,62 +1242,29 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     Q.k2[j] = t.k2;
     Q.evt[j] = t.evt;
     Q.nstep[j] = t.nstep;
-    Q.meta[j] = (uint32_t)t.sp | ((uint32_t)t.vol << 2);
+    Q.meta[j] = make_meta(t.sp, (uint32_t)t.vol);
     Q.src[j] = t.src;
-  }
-  if (!usable || !(stepped || vol_out)) return;
-  // ---- tallies of the event slot (deposits are scored in the pre-step volume)
-  const uint32_t e = t.evt;
-  const double sc = P.scale[e];
-  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + V.vbin[vol_out ? 0 : (int)vol]],
-                             fixed_point(o.dep, sc));
-  if (o.esc > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 0], fixed_point(o.esc, sc));
-  if (o.killed > 0.0) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(o.killed, sc));
-  if (o.escaped) {
-    const double tt = (log(o.esc) - P.lnE0) * P.inv_dlnE;
-    const int b = !(tt > 0.0) ? 0 : (tt >= (double)(kGrid - 1) ? kGrid - 1 : (int)tt);
-    atomicAdd(&P.esc_hist[t.sp * kGrid + b], 1ull);
-  }
-  if (o.dest == -2) count_done(P, e, -1);
-  if (rec && stepped) {
-    ems_step_record& r = rec[t.src];
-    r.dep = o.dep;
-    r.esc = o.esc;
-    r.killed = o.killed;
-    r.step_len = o.step_len;
-    r.limiter = o.limiter;
-    r.process = o.process;
-    r.n_pair = 0;
-    r.n_annih = 0;
-    r.n_out = o.dest == -1 ? 1 : 0;
-    r.escaped = o.escaped;
   }
 }
 
 // Part 1 as a kernel, one chunk per block: pool sizes come from the admission
-// cursors and the deferral bound k = min(n, (cap - n)/2) is taken on the device, so
-// the host launches an upper bound of blocks and the surplus exits at once.
+// cursors, so the host launches an upper bound of blocks and the surplus exits at
+// once.  Every track of the pool is stepped (output room is kept by the
+// interaction kernel, which puts off interactions that would not fit).
 template <class R, bool FIELD, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t N, int cur,
-                                                      IQueue Q, ems_step_record* rec,
-                                                      uint32_t cap) {
+                                                      IQueue Q, ems_step_record* rec) {
   const unsigned long long a = *ctr_line(P, kLAdmit);
   const uint32_t nG = lo32(a), nC = hi32(a), n = nG + nC;
-  const uint32_t k = n > cap ? 0u : min(n, (cap - n) / 2u);
-  const uint32_t kG = min(nG, k), kC = min(nC, k - kG);
   const uint32_t nbG = (nG + kBlock - 1) / kBlock, nbC = (nC + kBlock - 1) / kBlock;
   if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
     unsigned long long* st = ctr_line(P, kLStats);
     atomicAdd(&st[kSIn], (unsigned long long)n);
-    atomicAdd(&st[kSStepped], (unsigned long long)k);
-    atomicAdd(&st[kSStepG], (unsigned long long)kG);
-    atomicAdd(&st[kSStepC], (unsigned long long)kC);
     atomicAdd(&st[kSBusy], 1ull);
     atomicMax(&st[kSPeak], (unsigned long long)n);
-    if (k == 0) atomicAdd(&st[kSStall], 1ull);
   }
   if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
-  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, kG, nC, kC, nbG);
+  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG);
 }
 
 // Wave-aggregated append of one output stream (parent or secondary j) into the
@@ -1191,11 +1276,16 @@ struct OutBase {
 // One iteration, part 2: the interactions, for virtual block v.  Virtual blocks
 // are partitioned among the queues (block-uniform process, so a wavefront runs
 // one sampler); survivors and secondaries go to the output pool of their class.
+//
+// Output room: after the iteration the pool holds the transport survivors s, one
+// track per put-off interaction and at most three per interaction done, so with
+// the queues' entries ranked in queue order, entry r is done iff
+// r < L = (bound - s - sum of queue sizes) / 2 and the pool stays within `bound`.
 template <class R>
 __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q, const Pool& S,
                                                uint32_t N, int cur, ems_step_record* rec,
-                                               uint32_t v) {
-  uint32_t start = 0, qsel = kNumQueues, cnt = 0;
+                                               uint32_t v, uint32_t bound) {
+  uint32_t start = 0, qsel = kNumQueues, cnt = 0, before = 0, total = 0;
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) {
     const uint32_t c = queue_size(P, q);
@@ -1203,15 +1293,24 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     if (qsel == kNumQueues && v < start + nb) {
       qsel = q;
       cnt = c;
+      before = total;
     } else if (qsel == kNumQueues) {
       start += nb;
     }
+    total += c;
   }
   if (qsel == kNumQueues) return;  // (uniform) beyond the work
+  const unsigned long long so = *ctr_line(P, kLOut);
+  const uint64_t used = (uint64_t)lo32(so) + hi32(so) + total;
+  const uint32_t limit = used < bound ? (uint32_t)((bound - used) / 2) : 0u;
+  __shared__ Agg sh_agg;
+  agg_init(sh_agg);
+  __syncthreads();  // the table is empty before any lane inserts
   const int q = (int)qsel;
   const uint32_t i = (v - start) * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = i < cnt;
+  const bool put_off = valid && before + i >= limit;
   Track t{};
   Emit o{};
   bool alive = false, looped = false;
@@ -1231,13 +1330,38 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     t.nstep = Q.nstep[j];
     const uint32_t meta = Q.meta[j];
     t.sp = (int)(meta & 3u);
-    t.vol = (int)(meta >> 2);
+    t.vol = (int)(meta >> 6);
     t.src = Q.src[j];
     t.nlam = -1.0;
-    interact<R>(P, q, t, o, alive);
-    if (alive && t.nstep >= P.max_steps) {  // looper cap after the interaction
-      alive = false;
-      looped = true;
+    if (put_off) {
+      alive = true;  // back to the pool unchanged, flagged with its queue
+    } else {
+      interact<R>(P, q, t, o, alive);
+      if (alive && t.nstep >= P.max_steps) {  // looper cap after the interaction
+        alive = false;
+        looped = true;
+      }
+    }
+  }
+  // ---- scores of the event slot
+  if (valid) {
+    const uint32_t e = t.evt;
+    const double sc = P.scale[e];
+    if (o.dep > 0.0)
+      agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)P.vbin[t.vol]),
+              fixed_point(o.dep, sc));
+    if (o.n_pair) agg_add(P, sh_agg, agg_key(kTagLedger + 2, e), (unsigned long long)o.n_pair);
+    if (o.n_annih) agg_add(P, sh_agg, agg_key(kTagLedger + 3, e), (unsigned long long)o.n_annih);
+    if (looped) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(t.T, sc));
+    const int delta = (alive ? 1 : 0) + o.nsec - 1;
+    if (delta) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)delta);
+    if (rec) {
+      ems_step_record& r = rec[t.src];
+      r.dep += o.dep;
+      r.n_pair = o.n_pair;
+      r.n_annih = o.n_annih;
+      r.n_out = (alive ? 1 : 0) + o.nsec;
+      if (looped) r.killed += t.T;
     }
   }
   // ---- outputs: stream 0 = parent, 1..3 = secondaries, each to its class pool
@@ -1252,16 +1376,18 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   const uint32_t nc0 = __popcll(mc0), nc1 = __popcll(mc1), nc2 = __popcll(mc2), nc3 = __popcll(mc3);
   // block-level reservation of the two output pools, one atomic per block and pool
   constexpr int kW = kBlock / 64;
-  __shared__ uint32_t sh_cnt[kW][2];
+  __shared__ uint32_t sh_cnt[kW][3];
   __shared__ uint32_t sh_base[2];
   const int wave = threadIdx.x >> 6;
+  const uint64_t moff = __ballot(put_off);
   __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
     sh_cnt[wave][0] = ng0 + ng1 + ng2 + ng3;
     sh_cnt[wave][1] = nc0 + nc1 + nc2 + nc3;
+    sh_cnt[wave][2] = (uint32_t)__popcll(moff);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // after the transport survivors: this kernel's own counter
     uint32_t a = 0, b = 0;
 #pragma unroll
     for (int w2 = 0; w2 < kW; ++w2) {
@@ -1269,11 +1395,21 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
       b += sh_cnt[w2][1];
     }
     unsigned long long old = 0;
-    if (a | b) old = atomicAdd(ctr_line(P, kLOut), ((unsigned long long)b << 32) | a);
-    sh_base[0] = lo32(old);
-    sh_base[1] = hi32(old);
+    if (a | b) old = atomicAdd(ctr_line(P, kLOutI), ((unsigned long long)b << 32) | a);
+    sh_base[0] = lo32(so) + lo32(old);
+    sh_base[1] = hi32(so) + hi32(old);
+  } else if (threadIdx.x == 64) {
+    uint32_t d = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kW; ++w2) d += sh_cnt[w2][2];
+    if (d) atomicAdd(&stat_line(P)[kSDeferred], (unsigned long long)d);
+    // the whole capacity in use, no room for any interaction and nothing else in
+    // flight: the pool cannot progress
+    if (v == 0 && limit == 0 && total > 0 && lo32(so) + hi32(so) == 0 && bound >= N)
+      atomicAdd(&ctr_line(P, kLStats)[kSStall], 1ull);
   }
-  __syncthreads();
+  __syncthreads();  // also completes every lane's score inserts
+  agg_flush(P, sh_agg);
   uint32_t bg = sh_base[0], bc = sh_base[1];
   for (int w2 = 0; w2 < wave; ++w2) {
     bg += sh_cnt[w2][0];
@@ -1284,6 +1420,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     const size_t j = g0 ? offG + bg + lanes_below(mg0, lane) : offC + bc + lanes_below(mc0, lane);
     write_track(S, j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, -1.0, t.k0, t.k1, t.k2,
                 t.evt, t.nstep);
+    if (put_off) S.meta[j] = make_pending_meta(t.sp, q, (uint32_t)t.vol);
     if (rec) S.src[j] = t.src;
   }
   if (h1) {
@@ -1304,34 +1441,20 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     write_track(S, j, o.s2.sp, t.vol, t.x, t.y, t.z, o.s2.u, o.s2.v, o.s2.w, o.s2.T, -1.0,
                 o.s2.k0, o.s2.k1, o.s2.k2, t.evt, 0u);
   }
-  if (!valid) return;
-  const uint32_t e = t.evt;
-  if (o.dep > 0.0) atomicAdd(&P.tally[(size_t)e * P.nbins + P.vbin[t.vol]], fixed_point(o.dep, P.scale[e]));
-  if (o.n_pair) atomicAdd(&P.ledger[(size_t)e * kLedger + 2], (unsigned long long)o.n_pair);
-  if (o.n_annih) atomicAdd(&P.ledger[(size_t)e * kLedger + 3], (unsigned long long)o.n_annih);
-  if (looped) atomicAdd(&P.ledger[(size_t)e * kLedger + 1], fixed_point(t.T, P.scale[e]));
-  count_done(P, e, (alive ? 1 : 0) + o.nsec - 1);
-  if (rec) {
-    ems_step_record& r = rec[t.src];
-    r.dep += o.dep;
-    r.n_pair = o.n_pair;
-    r.n_annih = o.n_annih;
-    r.n_out = (alive ? 1 : 0) + o.nsec;
-    if (looped) r.killed += t.T;
-  }
 }
 
 // Part 2 as a kernel, one virtual block of the queues per block.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool S, uint32_t N,
-                                                     int cur, ems_step_record* rec) {
-  interact_chunk<R>(P, Q, S, N, cur, rec, blockIdx.x);
+                                                     int cur, ems_step_record* rec, uint32_t bound) {
+  interact_chunk<R>(P, Q, S, N, cur, rec, blockIdx.x, bound);
 }
 
 // Start of an iteration.  explicit_counts: begin a sync interval -- clear every
 // counter line and set the admission cursors to (nG, nC).  Otherwise continue from
-// the previous iteration: its output counts become this iteration's pool sizes,
-// its output and queue sizes are added to the interval statistics and cleared.
+// the previous iteration: its output counts (transport survivors plus tracks
+// written by the interaction kernel) become this iteration's pool sizes, its output
+// and queue sizes are added to the interval statistics and cleared.
 __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint32_t nG,
                              uint32_t nC) {
   const int j = threadIdx.x;
@@ -1341,7 +1464,7 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
     return;
   }
   if (j != 0) return;
-  const unsigned long long out = ctr[kLOut * kLineWords];
+  const unsigned long long out = ctr[kLOut * kLineWords] + ctr[kLOutI * kLineWords];
   unsigned long long queued = 0;
   for (int l = 0; l < 4; ++l) {
     const unsigned long long v = ctr[(kLQueue + l) * kLineWords];
@@ -1352,6 +1475,7 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
   ctr[kLStats * kLineWords + kSQueued] += queued;
   ctr[kLAdmit * kLineWords] = out;
   ctr[kLOut * kLineWords] = 0ull;
+  ctr[kLOutI * kLineWords] = 0ull;
 }
 
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
@@ -1377,7 +1501,7 @@ __global__ void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur, uint32_t
   const int vol = locate(P, x, y, z, u, v, w);
   const size_t k = buf_off(!g, cur, N) + (g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane));
   write_track(S, k, sp, 0, x, y, z, u, v, w, q.T[r], -1.0, a, b, cc, q.slot[r], 0u);
-  S.meta[k] = (uint32_t)sp | ((vol < 0 ? kVolOut : (uint32_t)vol) << 2);
+  S.meta[k] = make_meta(sp, vol < 0 ? kVolOut : (uint32_t)vol);
 }
 
 // Copy a batch's primaries into the ring at tail; row r belongs to the event e with
@@ -1499,7 +1623,7 @@ __global__ void k_pool_dump(Pool p, ems_track_soa s, uint32_t n, uint32_t off) {
   s.event[j] = p.evt[i];
   s.nstep[j] = p.nstep[i];
   s.species[j] = (int32_t)(p.meta[i] & 3u);
-  s.vol[j] = (int32_t)(p.meta[i] >> 2);
+  s.vol[j] = (int32_t)(p.meta[i] >> 6);
 }
 
 }  // namespace ems
@@ -1514,7 +1638,6 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n
 // size (the sizes themselves stay on the device).
 hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur, const IQueue& Q,
                             uint32_t bound, bool mixed, ems_step_record* rec, hipStream_t s) {
-  const uint32_t cap = N;
   const dim3 b(kBlock);
   const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
   const bool field = P.bz != 0.0;
@@ -1523,7 +1646,7 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   const bool staged = lds <= kStageMaxBytes;
   const uint32_t sh = staged ? lds : 0u;
 #define EMS_LAUNCH_T(R, F, ST) \
-  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec, cap)
+  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec)
   if (mixed) {
     if (field) {
       if (staged) EMS_LAUNCH_T(float, true, true);
@@ -1544,8 +1667,8 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
 #undef EMS_LAUNCH_T
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec);
-  else hipLaunchKernelGGL(k_interact<double>, gI, b, 0, s, P, Q, S, N, cur, rec);
+  if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
+  else hipLaunchKernelGGL(k_interact<double>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
   return hipGetLastError();
 }
 
