@@ -76,18 +76,28 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_calorimeter_fp64_tra
 def measured_traffic(args):
     """HBM bytes per step iteration from the committed FETCH_SIZE / WRITE_SIZE counters
     of the default FP64 calorimeter workload, or None when they do not apply (another
-    workload or precision, or kernel source changed since they were taken)."""
-    import hashlib
+    workload or precision, or kernel code changed since they were taken)."""
     if args.precision != "fp64" or args.events != 100_000 or args.energy != 1000.0:
         return None
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        with open(os.path.join(ROOT, t["kernel_source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_digest(os.path.join(ROOT, t["kernel_source"]))
     except (OSError, KeyError, ValueError):
         return None
-    return float(t["bytes_per_iteration"]) if sha == t["kernel_source_sha256"] else None
+    return float(t["bytes_per_iteration"]) if sha == t["kernel_code_sha256"] else None
+
+
+def kernel_source_digest(path):
+    """sha256 of a C++ source with comments and blank space removed (code only)."""
+    import hashlib
+    import re
+    with open(path) as f:
+        src = f.read()
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def run_transport(ems, wl, n_events, args, precision, log_name):

@@ -1,15 +1,19 @@
 // ems_kernels.hip -- gfx950 kernels of the electromagnetic-shower step loop.
 //
 // One lane per track (paper Sec. 2.1 "Code Architecture").  A step iteration is
-// one fused kernel over the compacted pool: cross-section lookup, interaction
-// length sampling, continuous step limit, distance to boundary, move and
-// continuous loss, discrete interaction with secondary emission, cutoffs, and
-// tallies (paper Sec. 2.2 items (i)-(vi)); survivors and secondaries are then
-// written, compacted, into the other pool buffer with one atomic per wavefront
-// (ballot + popcount prefix), the wave-aggregated form of the paper's atomic
-// stack allocator (Sec. 2.1).  Nothing here is a dense contraction, so there is
-// no MFMA: the kernel streams SoA state (coalesced 64-lane accesses) and reads
-// the small cross-section tables through the L1/L2 caches.
+// two kernels over the compacted pools (paper Sec. 3.2: a step is several
+// kernels with synchronisation points).  k_transport: cross-section lookup,
+// interaction-length sampling, continuous step limit, distance to boundary (or a
+// curved move in a field), move and continuous loss, cutoffs, process selection
+// (paper Sec. 2.2 items (i)-(vi)); survivors go to the other pool buffer, tracks
+// that interact to one queue per process.  k_interact: the interaction of one
+// process per block, secondary emission, and the room check that puts off
+// interactions which would not fit.  Outputs are reserved with one atomic per
+// block and stream (ballot + popcount prefix in LDS), the block-aggregated form
+// of the paper's atomic stack allocator (Sec. 2.1); per-event scores are summed
+// per block in LDS before one global atomic per key.  Nothing here is a dense
+// contraction, so there is no MFMA: the kernels stream SoA state (coalesced
+// 64-lane accesses) and read tables and geometry from a per-block LDS copy.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the track's
 // 96-bit lineage key and its own step count, so a track's history does not
