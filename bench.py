@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool", type=int, default=1 << 24)
     ap.add_argument("--budget", type=float, default=2.5e7, help="energy in flight, MeV")
-    ap.add_argument("--per-sync", type=int, default=2,
+    ap.add_argument("--per-sync", type=int, default=4,
                     help="step iterations launched back to back between host synchronisations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")

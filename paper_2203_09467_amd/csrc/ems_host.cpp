@@ -506,6 +506,9 @@ struct IntervalOut {
 };
 
 constexpr uint32_t kBoundMargin = 65536;
+// steps a track may take in one transport launch while it neither interacts nor
+// dies (single-step diagnostics take one)
+constexpr uint32_t kStepsPerLaunch = 4;
 constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
 
 ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
@@ -529,7 +532,8 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   for (int j = 0; j < iters; ++j) {
     if (j > 0) HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
     if (x->ev[2 * j]) HIP_OK(hipEventRecord(x->ev[2 * j], s));
-    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, mixed, rec, s));
+    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, full_room ? 1u : kStepsPerLaunch,
+                            mixed, rec, s));
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
     x->cur = 1 - x->cur;
   }

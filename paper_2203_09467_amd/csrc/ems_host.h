@@ -12,7 +12,8 @@ int build_physics_tables(const ems_material* mats, int n_mats, const ems_physics
                          std::vector<double>& tab, MatParams* mp);
 
 hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur, const IQueue& Q,
-                            uint32_t bound, bool mixed, ems_step_record* rec, hipStream_t s);
+                            uint32_t bound, uint32_t msteps, bool mixed, ems_step_record* rec,
+                            hipStream_t s);
 hipError_t launch_iter_begin(unsigned long long* ctr, bool explicit_counts, uint32_t nG,
                              uint32_t nC, hipStream_t s);
 hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t N, int cur,

@@ -1078,7 +1078,7 @@ template <class R, bool FIELD, bool STAGED>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
                                                 uint32_t c, uint32_t nG, uint32_t nC,
-                                                uint32_t nbG) {
+                                                uint32_t nbG, uint32_t msteps) {
   const bool cblk = c >= nbG;
   const size_t io = buf_off(cblk, cur, N), oo = buf_off(cblk, 1 - cur, N);
   const uint32_t n = cblk ? nC : nG;
@@ -1090,7 +1090,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   o.process = -1;
   o.dest = -2;
   bool stepped = false, vol_out = false, pending = false;
-  uint32_t vol = 0;
+  uint32_t vol = 0, nsteps = 0;
   int pq = 0;
   // every field of the state is loaded at once (one round trip), checked after
   if (valid) {
@@ -1132,19 +1132,31 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       if (pending) {
         o.dest = pq;  // its interaction, put off last iteration, is done now
       } else {
-        transport<R, FIELD>(P, V, t, o);
+        // up to msteps steps while the track survives without interacting; each
+        // step's deposit is scored in its pre-step volume
+        const uint32_t e = t.evt;
+        const double sc = P.scale[e];
+        for (uint32_t m = 0; m < msteps; ++m) {
+          const int v0 = t.vol;
+          o = Moved{};
+          o.process = -1;
+          o.dest = -2;
+          transport<R, FIELD>(P, V, t, o);
+          ++nsteps;
+          if (o.dep > 0.0)
+            agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)V.vbin[v0]),
+                    fixed_point(o.dep, sc));
+          if (o.dest != -1) break;
+        }
         stepped = true;
       }
     }
   }
 
-  // ---- scores of the event slot (deposits are scored in the pre-step volume)
+  // ---- scores of the event slot
   if (usable && (stepped || vol_out)) {
     const uint32_t e = t.evt;
     const double sc = P.scale[e];
-    if (o.dep > 0.0)
-      agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)V.vbin[vol_out ? 0 : (int)vol]),
-              fixed_point(o.dep, sc));
     if (o.esc > 0.0) agg_add(P, sh_agg, agg_key(kTagLedger + 0, e), fixed_point(o.esc, sc));
     if (o.killed > 0.0) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(o.killed, sc));
     if (o.escaped) {
@@ -1177,15 +1189,20 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   uint64_t mq[kNumQueues];
 #pragma unroll
   for (int q = 0; q < kNumQueues; ++q) mq[q] = __ballot(o.dest == q);
-  const uint64_t mpos = __ballot(stepped && t.sp == EMS_POSITRON);
-  const uint64_t mstep = __ballot(stepped), mpend = __ballot(pending && usable);
+  const uint64_t mpend = __ballot(pending && usable);
+  uint32_t wsteps = nsteps, wpos = t.sp == EMS_POSITRON ? nsteps : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    wsteps += __shfl_xor(wsteps, off);
+    wpos += __shfl_xor(wpos, off);
+  }
   __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
     sh_cnt[wave][0] = (uint32_t)__popcll(mS);
 #pragma unroll
     for (int q = 0; q < kNumQueues; ++q) sh_cnt[wave][1 + q] = (uint32_t)__popcll(mq[q]);
-    sh_cnt[wave][9] = (uint32_t)__popcll(mstep);
-    sh_cnt[wave][10] = (uint32_t)__popcll(mpos);
+    sh_cnt[wave][9] = wsteps;
+    sh_cnt[wave][10] = wpos;
     sh_cnt[wave][11] = (uint32_t)__popcll(mpend);
   }
   __syncthreads();
@@ -1210,7 +1227,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       sh_base[s0] = lo32(old);
       sh_base[s0 + 1] = hi32(old);
     } else {
-      // block statistics: photon or charged steps, positron steps, pending tracks
+      // block statistics: photon or charged track-steps, positron track-steps, pending tracks
       const uint32_t st = tot(9), pos = tot(10), pend = tot(11);
       unsigned long long* L = stat_line(P);
       if (st) atomicAdd(&L[cblk ? kSStepC : kSStepG], (unsigned long long)st);
@@ -1255,9 +1272,13 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // cursors, so the host launches an upper bound of blocks and the surplus exits at
 // once.  Every track of the pool is stepped (output room is kept by the
 // interaction kernel, which puts off interactions that would not fit).
+// At least four waves per SIMD (two blocks per CU) without a field: the loop of
+// steps would otherwise take twice the registers of one step and leave one block
+// per CU; the curved move needs the registers.
 template <class R, bool FIELD, bool STAGED>
-__global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t N, int cur,
-                                                      IQueue Q, ems_step_record* rec) {
+__global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
+                                                      IQueue Q, ems_step_record* rec,
+                                                      uint32_t msteps) {
   const unsigned long long a = *ctr_line(P, kLAdmit);
   const uint32_t nG = lo32(a), nC = hi32(a), n = nG + nC;
   const uint32_t nbG = (nG + kBlock - 1) / kBlock, nbC = (nC + kBlock - 1) / kBlock;
@@ -1268,7 +1289,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(Params P, Pool S, uint32_t
     atomicMax(&st[kSPeak], (unsigned long long)n);
   }
   if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
-  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG);
+  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG, msteps);
 }
 
 // Wave-aggregated append of one output stream (parent or secondary j) into the
@@ -1641,7 +1662,8 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n
 // One iteration: transport then interactions; `bound` is an upper bound of the pool
 // size (the sizes themselves stay on the device).
 hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur, const IQueue& Q,
-                            uint32_t bound, bool mixed, ems_step_record* rec, hipStream_t s) {
+                            uint32_t bound, uint32_t msteps, bool mixed, ems_step_record* rec,
+                            hipStream_t s) {
   const dim3 b(kBlock);
   const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
   const bool field = P.bz != 0.0;
@@ -1650,7 +1672,7 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   const bool staged = lds <= kStageMaxBytes;
   const uint32_t sh = staged ? lds : 0u;
 #define EMS_LAUNCH_T(R, F, ST) \
-  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec)
+  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec, msteps)
   if (mixed) {
     if (field) {
       if (staged) EMS_LAUNCH_T(float, true, true);
