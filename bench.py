@@ -8,9 +8,10 @@ sections, interaction lengths, step limits, boundaries, continuous loss,
 interactions, secondaries, compaction, tallies) with the primaries already
 resident in HBM.  value = track-steps / s over the timed steps.
 
-Also reported: the step kernel against the HBM roofline (algorithmic bytes =
-88 B read per track in the pool + 88 B written per surviving track or secondary,
-divided by the step kernels' summed HIP-event durations on their launch stream),
+Also reported: the step kernels against the HBM roofline (algorithmic bytes =
+88 B read per track in the pool + 88 B written per track left in the pools +
+2 x 80 B per track queued for an interaction, divided by the step kernels'
+summed HIP-event durations on their launch stream),
 and the CPU oracle timed on a bounded sample of the same workload on the host
 cores (cpu_baseline).
 """
@@ -27,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TRACK = 88  # SoA state of one track: 8 doubles + 6 words
+QUEUE_BYTES = 80      # queue entry: 7 doubles + 6 words (no interaction length)
 
 
 def log(msg):
@@ -214,7 +216,9 @@ def main():
     r = run_transport(ems, wl, args.events, args, prec, args.precision)
     value = r["steps"] / r["t"]
     st = r["stats"]
-    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out)
+    # state read and written once per launch, plus each queued track written to and
+    # read back from its interaction queue
+    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
     kernel_s = st.kernel_ms / 1e3
     achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
     out = {

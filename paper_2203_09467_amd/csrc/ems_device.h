@@ -19,7 +19,7 @@ constexpr int kLedger = 4;            // escaped (fixed point), killed (fixed po
 constexpr uint32_t kVolOut = 0x3FFFFFFu;  // meta volume of a primary that starts outside
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
-constexpr int kBlock = 512;
+constexpr int kBlock = 256;
 constexpr uint32_t kStageMaxBytes = 64u * 1024u;  // per-block LDS budget of the staged run data
 
 // Tracks in flight, SoA.  meta = species (bits 0-1) | pending (bit 2) | queue of

@@ -936,7 +936,7 @@ __device__ __forceinline__ unsigned long long fixed_point(double e, double scale
 // and changes of the events' alive counts -- are summed in an LDS hash table and
 // added to global memory once per distinct key.  The sums are integers (fixed-point
 // energies, counts), so grouping them changes no result.  Key = tag << 29 | index.
-constexpr int kAggSlots = 1024;
+constexpr int kAggSlots = 512;
 constexpr int kAggProbes = 32;
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
 enum AggTag : uint32_t {
@@ -982,7 +982,7 @@ __device__ __forceinline__ void agg_init(Agg& A) {
 // Insert with linear probing (bounded: a crowded table falls back to a global add).
 __device__ __forceinline__ void agg_add(const Params& P, Agg& A, uint32_t key,
                                         unsigned long long v) {
-  uint32_t h = (key * 0x9E3779B1u) >> 22;
+  uint32_t h = (key * 0x9E3779B1u) >> 23;  // top log2(kAggSlots) bits
 #pragma nounroll
   for (int p = 0; p < kAggProbes; ++p) {
     const uint32_t prev = atomicCAS(&A.key[h], kAggEmpty, key);
@@ -1272,9 +1272,9 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // cursors, so the host launches an upper bound of blocks and the surplus exits at
 // once.  Every track of the pool is stepped (output room is kept by the
 // interaction kernel, which puts off interactions that would not fit).
-// At least four waves per SIMD (two blocks per CU) without a field: the loop of
-// steps would otherwise take twice the registers of one step and leave one block
-// per CU; the curved move needs the registers.
+// At least four waves per SIMD without a field (four blocks of 256 per CU): the
+// loop of steps would otherwise take twice the registers of one step; the curved
+// move needs the registers.
 template <class R, bool FIELD, bool STAGED>
 __global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
                                                       IQueue Q, ems_step_record* rec,
