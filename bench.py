@@ -85,9 +85,11 @@ def measured_traffic(args):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         sha = kernel_source_digest(os.path.join(ROOT, t["kernel_source"]))
+        same = (sha == t["kernel_code_sha256"] and t["energy_budget_MeV"] == args.budget and
+                t["pool_slots"] == args.pool and t["iterations_per_sync"] == args.per_sync)
     except (OSError, KeyError, ValueError):
         return None
-    return float(t["bytes_per_iteration"]) if sha == t["kernel_code_sha256"] else None
+    return float(t["bytes_per_iteration"]) if same else None
 
 
 def kernel_source_digest(path):
@@ -176,7 +178,7 @@ def main():
     ap.add_argument("--energy", type=float, default=1000.0, help="primary energy, MeV")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool", type=int, default=1 << 24)
-    ap.add_argument("--budget", type=float, default=2.5e7, help="energy in flight, MeV")
+    ap.add_argument("--budget", type=float, default=1e8, help="energy in flight, MeV")
     ap.add_argument("--per-sync", type=int, default=4,
                     help="step iterations launched back to back between host synchronisations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -237,7 +239,8 @@ def main():
         "config": {"workload": f"calorimeter: {args.events} x {args.energy / 1000:g} GeV e- on "
                                "50 x (2 mm Pb + 5 mm LAr), 40x40 cm, 0.7 mm cut, seed 2",
                    "precision": args.precision, "pool_slots": args.pool,
-                   "energy_budget_MeV": args.budget, "iterations": r["iters"],
+                   "energy_budget_MeV": args.budget, "iterations_per_sync": args.per_sync,
+                   "iterations": r["iters"],
                    "peak_tracks_in_flight": r["peak"], "track_steps": r["steps"],
                    "ledger_max_rel_error": r["ledger_max"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

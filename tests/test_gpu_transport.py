@@ -85,12 +85,13 @@ def test_calorimeter_events(orc):
 
 
 def test_results_independent_of_pool_size_and_mix():
-    """A small pool (deferral active) and a different batch composition give bitwise the
-    same per-event tallies: tallies are fixed-point sums and streams are keyed per event."""
+    """A small pool (interactions put off for lack of room) and a different batch
+    composition give bitwise the same per-event tallies: tallies are fixed-point sums
+    and streams are keyed per event."""
     wl = W.calorimeter(60)
     big = _run_gpu(wl, wl.events)
-    small = _run_gpu(wl, wl.events, pool=1 << 13, energy_budget=8000.0)
-    assert small["progress"].deferred > 0 or small["progress"].peak_alive > 0
+    small = _run_gpu(wl, wl.events, pool=1 << 10, energy_budget=8000.0)
+    assert small["progress"].deferred > 0  # interactions were put off for lack of room
     assert np.array_equal(big["dep"], small["dep"])
     assert np.array_equal(big["ledger"], small["ledger"])
     alone = _run_gpu(wl, wl.events.subset([17]))
