@@ -69,7 +69,8 @@ def cpu_baseline(n_events, energy, seed, budget_s=12.0):
     total = sum(r[0] for r in res)
     return dict(value=total / wall, unit="track-steps/s", cores=len(jobs), kind="oracle",
                 sample=f"events 0..{n_sample - 1} of the benchmark batch ({total} track-steps, "
-                       f"{wall:.1f} s wall, {len(jobs)} processes)")
+                       f"{wall:.1f} s wall, {len(jobs)} processes)",
+                one_core_value=rate1, one_core_sample=f"events 0..19 ({steps} track-steps) in one process")
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_calorimeter_fp64_traffic.json")
@@ -223,6 +224,7 @@ def main():
     bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
     kernel_s = st.kernel_ms / 1e3
     achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    traffic = measured_traffic(args)
     out = {
         "metric": "track-steps/s (FP64 vs mixed-prec) + p50/p99 event latency, 1 MI355X",
         "value": value,
@@ -244,8 +246,9 @@ def main():
                    "peak_tracks_in_flight": r["peak"], "track_steps": r["steps"],
                    "ledger_max_rel_error": r["ledger_max"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per iteration",
+                     "measured_gbs": None if traffic is None else traffic / (kernel_s / max(st.launches, 1)) / 1e9,
                      "algorithmic_bytes_per_iteration": bytes_alg / max(st.launches, 1),
                      "kernel": "step kernels (k_transport + k_interact)",
                      "launches": st.launches,
