@@ -75,7 +75,7 @@ typedef struct {
 /* Step-kernel statistics accumulated since creation or the last reset. */
 typedef struct {
   uint64_t launches;
-  uint64_t tracks_in;   /* tracks read by the step kernel (stepped + deferred) */
+  uint64_t tracks_in;   /* tracks read by the transport kernel per launch, summed */
   uint64_t tracks_out;  /* tracks written (survivors + secondaries) */
   uint64_t queued;      /* tracks passed from transport to the interaction kernel */
   double kernel_ms;     /* summed durations (EMS_FLAG_TIME_STEPS), else 0 */
@@ -131,7 +131,8 @@ typedef struct {
   uint64_t queued_events;
   uint64_t iterations;       /* step iterations run by this call */
   uint64_t track_steps;      /* track-steps taken by this call */
-  uint64_t deferred;         /* track-steps deferred for lack of pool space */
+  uint64_t deferred;         /* interactions put off for lack of pool room (the track
+                                returns to the pool and does it in a later iteration) */
   uint64_t peak_alive;       /* largest pool occupancy seen by this call */
 } ems_progress;
 
@@ -179,9 +180,12 @@ ems_status init_geometry(ems_ctx* ctx, const ems_geometry* geom, void* stream);
  * max_iterations step iterations (< 0: until every submitted event is done).
  * Events are admitted whole, in submission order, while pool slots and the
  * energy budget allow; tracks of all admitted events share the pool and are
- * stepped together.  EMS_E_CAPACITY if the batch does not fit the free event
- * slots or the queue (nothing submitted), or if the pool can no longer make
- * progress.  progress (host) may be NULL. */
+ * stepped together (an iteration = one transport launch, in which a track takes
+ * up to four steps while it neither interacts nor dies, then one interaction
+ * launch; interactions that would overflow the pool are put off to a later
+ * iteration, which changes no result).  EMS_E_CAPACITY if the batch does not fit
+ * the free event slots or the queue (nothing submitted), or if the pool can no
+ * longer make progress.  progress (host) may be NULL. */
 ems_status transport_events(ems_ctx* ctx, const ems_event_batch* batch, int32_t max_iterations,
                             void* stream, ems_progress* progress);
 

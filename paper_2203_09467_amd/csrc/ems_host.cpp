@@ -1,14 +1,16 @@
 // ems_host.cpp -- C ABI of the step loop: context, workspace carving, geometry,
 // event slots and queue, the host iteration loop, tally readout.
 //
-// The host loop per iteration (paper Sec. 3.2: a step is several kernels with
-// synchronisation points; events are batched to keep enough tracks in flight):
+// The host loop (paper Sec. 3.2: a step is several kernels with synchronisation
+// points; events are batched to keep enough tracks in flight), per sync interval:
 //   1. admit whole queued events while pool room and the energy budget allow
-//      (one kernel appending primaries to the pool);
-//   2. one fused step kernel over the pool, writing the compacted next pool;
-//   3. read back the pool size and the list of events that just finished.
+//      (one kernel appending primaries to the pools);
+//   2. K iterations enqueued back to back, each k_iter_begin (pool sizes from the
+//      previous outputs, on the device), k_transport (up to four steps per track),
+//      k_interact (interactions, secondaries, room check);
+//   3. one readback of the counters and the list of events that just finished.
 // The step count of a track, not the iteration, keys its random numbers, so
-// admission order, deferral and pool size change no result.
+// admission order, put-off interactions and pool size change no result.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

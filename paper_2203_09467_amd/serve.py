@@ -34,6 +34,7 @@ def serve(ctx, events, device_events: DeviceEvents = None, iterations: int = 8,
     index = {int(e): i for i, e in enumerate(events.event_ids)}
     in_flight = []
     nxt = 0
+    max_batch = max(n, 1)  # halved after a refusal for lack of event slots, doubled after a success
     steps = 0
     peak_events = 0
     t0 = time.perf_counter()
@@ -42,7 +43,7 @@ def serve(ctx, events, device_events: DeviceEvents = None, iterations: int = 8,
         if now > time_limit:
             raise RuntimeError(f"serving did not finish within {time_limit} s")
         b = nxt
-        while b < n and arrival[b] <= now:
+        while b < n and arrival[b] <= now and b - nxt < max_batch:
             b += 1
         batch = None
         if b > nxt:
@@ -57,9 +58,11 @@ def serve(ctx, events, device_events: DeviceEvents = None, iterations: int = 8,
             if batch is not None:
                 in_flight.extend(int(e) for e in batch.ids)
                 nxt = b
-        except EmsError as e:  # no free slots or queue room: retry after others finish
-            if e.status != -3:
+                max_batch = min(max(n, 1), 2 * max_batch)
+        except EmsError as e:  # no free slots or queue room: retry after others finish,
+            if e.status != -3:  # with a smaller batch (the library takes a batch whole)
                 raise
+            max_batch = max(1, (b - nxt) // 2)
             pr = ctx.transport(None, iterations)
         steps += pr.track_steps
         peak_events = max(peak_events, len(in_flight))
