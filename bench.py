@@ -170,6 +170,35 @@ def run_serving(ems, args, precision):
             "peak_events_in_flight": res["peak_events"]}
 
 
+def run_photon_sat(ems, n, args):
+    """Photon-only cube with n one-photon events in one launch sequence (the small
+    photon workload at sizes that fill the GPU)."""
+    import torch
+    import workloads as W
+    wl = W.photon_cube(n)
+    ctx = ems.Context(pool_capacity=4 * n, max_events=n, max_bins=wl.geometry.n_bins,
+                      queue_capacity=n, seed=wl.seed, precision=ems.EMS_FP64, time_steps=True,
+                      iterations_per_sync=args.per_sync)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    dev = ems.DeviceEvents(wl.events)
+    torch.cuda.synchronize()
+    ctx.step_stats(reset=True)
+    t0 = time.perf_counter()
+    pr = ctx.transport(dev, -1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = ctx.step_stats()
+    ctx.close()
+    kernel_s = st.kernel_ms / 1e3
+    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
+    achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    log(f"photon cube {n}: {pr.track_steps} track-steps in {t:.3f} s, {pr.iterations} iterations")
+    return {"primaries": n, "value": pr.track_steps / t, "unit": "track-steps/s",
+            "step_kernels_value": pr.track_steps / kernel_s if kernel_s > 0 else None,
+            "iterations": pr.iterations, "peak_tracks_in_flight": pr.peak_alive,
+            "roofline_achieved_gbs": achieved, "roofline_frac": achieved / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +214,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-photon-sat", action="store_true",
+                    help="skip the photon-cube runs at 1e6 and 1e7 primaries")
     ap.add_argument("--serve-events", type=int, default=1000)
     ap.add_argument("--serve-budget", type=float, default=5e7,
                     help="energy in flight of the serving loop, MeV")
@@ -269,6 +300,10 @@ def main():
                           "mixed": run_serving(ems, args, ems.EMS_MIXED),
                           "workload": "calorimeter geometry; events of U{1..500} primaries "
                                       "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
+    if not args.no_photon_sat:
+        out["photon_cube_sat"] = {
+            "workload": "10 MeV photons into a 10 cm Pb cube, one photon per event, FP64",
+            "runs": [run_photon_sat(ems, n, args) for n in (1_000_000, 10_000_000)]}
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the oracle on a sample of the batch")
         out["cpu_baseline"] = cpu_baseline(args.events, args.energy, seed)

@@ -429,9 +429,10 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
       return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
   }
   {
-    std::unordered_map<uint32_t, int> seen;
-    for (uint32_t e = 0; e < ne; ++e)
-      if (seen[b->event_ids[e]]++) return fail(EMS_E_ARG, "transport_events: duplicate event id in batch");
+    std::vector<uint32_t> ids(b->event_ids, b->event_ids + ne);
+    if (!std::is_sorted(ids.begin(), ids.end())) std::sort(ids.begin(), ids.end());
+    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+      return fail(EMS_E_ARG, "transport_events: duplicate event id in batch");
   }
   std::vector<uint32_t> slots(ne);
   for (uint32_t e = 0; e < ne; ++e) slots[e] = x->free_slots[x->free_slots.size() - 1 - e];
@@ -441,17 +442,17 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
   HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
                         b->energy, b->pos, b->dir, (uint32_t)n, s));
-  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, ne, x->e_in, x->scale, s));
-  // primary energy per slot (admission energy budget) and photons per event (pool sizes)
-  std::vector<double> ein(x->cfg.max_events);
+  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, ne, x->e_in, x->scale,
+                           x->stage_out, s));
+  // primary energy per event (admission energy budget) and photons per event (pool sizes)
+  std::vector<double> ev_e(ne);
   std::vector<int32_t> sp(n);
-  HIP_OK(hipMemcpyAsync(ein.data(), x->e_in, ein.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(ev_e.data(), x->stage_out, ne * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(sp.data(), b->species, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  std::vector<double> ev_e(ne);
-  for (uint32_t e = 0; e < ne; ++e) ev_e[e] = ein[slots[e]];
   for (uint64_t r = 0; r < n; ++r)
     if (sp[r] < 0 || sp[r] > 2) return fail(EMS_E_ARG, "transport_events: species must be 0, 1 or 2");
+  x->id_to_slot.reserve(x->id_to_slot.size() + ne);
   for (uint32_t e = 0; e < ne; ++e) {
     const uint32_t sl = slots[e];
     x->free_slots.pop_back();

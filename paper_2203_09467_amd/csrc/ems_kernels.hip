@@ -1560,7 +1560,7 @@ __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint
 // primaries' kinetic energies; fixed-point scale 2^(61 - ceil(log2 E_in)) keeps the
 // sum of its deposits below 2^61 quanta; tallies and ledger zeroed.
 __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots,
-                             const double* T, double* e_in, double* scale) {
+                             const double* T, double* e_in, double* scale, double* e_row) {
   const uint32_t e = blockIdx.x;
   const int64_t a = off[e], b = off[e + 1];
   __shared__ double part[kBlock];
@@ -1582,6 +1582,7 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
       frexp(E, &ex);  // E < 2^ex
     }
     e_in[slot] = E;
+    e_row[e] = E;  // per batch row, read back by the host
     scale[slot] = ldexp(1.0, 61 - ex);
     P.alive[slot] = (int)(b - a);
   }
@@ -1724,10 +1725,10 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
 
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
                              const double* T, uint32_t n_events, double* e_in, double* scale,
-                             hipStream_t s) {
+                             double* e_row, hipStream_t s) {
   if (n_events == 0) return hipSuccess;
   hipLaunchKernelGGL(k_event_init, dim3(n_events), dim3(kBlock), 0, s, P, off, slots, T, e_in,
-                     scale);
+                     scale, e_row);
   return hipGetLastError();
 }
 
