@@ -199,6 +199,39 @@ def run_photon_sat(ems, n, args):
             "roofline_achieved_gbs": achieved, "roofline_frac": achieved / HBM_PEAK_GBS}
 
 
+def run_barrel(ems, n, args, precision):
+    """Barrel with B_z = 1 T: n events of one primary (60/20/20 % e-/e+/photon,
+    log-uniform 1-100 GeV, |eta| < 1.5), RK4 field propagation."""
+    import torch
+    import workloads as W
+    wl = W.barrel(n)
+    ctx = ems.Context(pool_capacity=args.pool, max_events=n, max_bins=wl.geometry.n_bins,
+                      queue_capacity=n, seed=wl.seed, precision=precision, energy_budget=args.budget,
+                      time_steps=True, iterations_per_sync=args.per_sync)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    dev = ems.DeviceEvents(wl.events)
+    torch.cuda.synchronize()
+    ctx.step_stats(reset=True)
+    t0 = time.perf_counter()
+    pr = ctx.transport(dev, -1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = ctx.step_stats()
+    dep, led, status = ctx.read(wl.events.event_ids)
+    ctx.close()
+    assert (status == 0).all()
+    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
+    kernel_s = st.kernel_ms / 1e3
+    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
+    achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    log(f"barrel {n} ({'fp64' if precision == ems.EMS_FP64 else 'mixed'}): {pr.track_steps} "
+        f"track-steps in {t:.3f} s, {pr.iterations} iterations")
+    return {"value": pr.track_steps / t, "unit": "track-steps/s", "track_steps": pr.track_steps,
+            "iterations": pr.iterations, "peak_tracks_in_flight": pr.peak_alive,
+            "roofline_achieved_gbs": achieved, "roofline_frac": achieved / HBM_PEAK_GBS,
+            "ledger_max_rel_error": float(np.abs(bal / led[:, 0]).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-barrel", action="store_true", help="skip the barrel (field) runs")
+    ap.add_argument("--barrel-events", type=int, default=20_000)
     ap.add_argument("--no-photon-sat", action="store_true",
                     help="skip the photon-cube runs at 1e6 and 1e7 primaries")
     ap.add_argument("--serve-events", type=int, default=1000)
@@ -300,6 +335,14 @@ def main():
                           "mixed": run_serving(ems, args, ems.EMS_MIXED),
                           "workload": "calorimeter geometry; events of U{1..500} primaries "
                                       "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
+    if not args.no_barrel:
+        fm = run_barrel(ems, args.barrel_events, args, ems.EMS_MIXED)
+        fd = run_barrel(ems, args.barrel_events, args, ems.EMS_FP64)
+        out["barrel_field"] = {
+            "workload": f"{args.barrel_events} primaries (60/20/20 % e-/e+/photon), log-uniform "
+                        "1-100 GeV, |eta| < 1.5, barrel of 5 Si shells + 50 Pb/LAr layers, "
+                        "B_z = 1 T, RK4 tolerance 1e-5 cm, seed 4",
+            "mixed": fm, "fp64": fd, "mixed_speedup_vs_fp64": fm["value"] / fd["value"]}
     if not args.no_photon_sat:
         out["photon_cube_sat"] = {
             "workload": "10 MeV photons into a 10 cm Pb cube, one photon per event, FP64",

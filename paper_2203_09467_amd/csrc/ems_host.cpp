@@ -512,6 +512,10 @@ constexpr uint32_t kBoundMargin = 65536;
 // steps a track may take in one transport launch while it neither interacts nor
 // dies (single-step diagnostics take one)
 constexpr uint32_t kStepsPerLaunch = 4;
+// a pool this small cannot fill the GPU: its launches are latency bound, so each
+// takes more steps per track (the tail of a run, long-lived loopers)
+constexpr uint64_t kTailTracks = 131072;
+constexpr uint32_t kTailStepsPerLaunch = 32;
 constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
 
 ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
@@ -532,11 +536,11 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   const uint64_t n0 = (uint64_t)x->nG + x->nC;
   const uint32_t bound =
       full_room ? cap : (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(n0, 2 * n0 + kBoundMargin));
+  const uint32_t msteps = full_room ? 1u : (n0 < kTailTracks ? kTailStepsPerLaunch : kStepsPerLaunch);
   for (int j = 0; j < iters; ++j) {
     if (j > 0) HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
     if (x->ev[2 * j]) HIP_OK(hipEventRecord(x->ev[2 * j], s));
-    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, full_room ? 1u : kStepsPerLaunch,
-                            mixed, rec, s));
+    HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, msteps, mixed, rec, s));
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
     x->cur = 1 - x->cur;
   }
