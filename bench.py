@@ -9,9 +9,10 @@ interactions, secondaries, compaction, tallies) with the primaries already
 resident in HBM.  value = track-steps / s over the timed steps.
 
 Also reported: the step kernels against the HBM roofline (algorithmic bytes =
-88 B read per track in the pool + 88 B written per track left in the pools +
-2 x 80 B per track queued for an interaction, divided by the step kernels'
-summed HIP-event durations on their launch stream),
+160 B per FP64 track-step -- the minimal track state read and written by a fused
+step -- times the track-steps of an iteration, divided by the step kernels'
+HIP-event duration per iteration on their launch stream; the bytes this design
+moves per iteration and the counter-measured traffic are reported beside it),
 and the CPU oracle timed on a bounded sample of the same workload on the host
 cores (cpu_baseline).
 """
@@ -29,6 +30,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TRACK = 88  # SoA state of one track: 8 doubles + 6 words
 QUEUE_BYTES = 80      # queue entry: 7 doubles + 6 words (no interaction length)
+# algorithmic bytes per track-step of a fused step with the minimal state (read +
+# write): FP64, and mixed precision with an FP32 interaction length
+BYTES_PER_STEP = {"fp64": 160, "mixed": 152}
+
+
+def state_bytes(st):
+    """Bytes this design moves: state read and written once per launch, queue round trips."""
+    return BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
 
 
 def log(msg):
@@ -190,8 +199,7 @@ def run_photon_sat(ems, n, args):
     st = ctx.step_stats()
     ctx.close()
     kernel_s = st.kernel_ms / 1e3
-    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
-    achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    achieved = BYTES_PER_STEP["fp64"] * pr.track_steps / kernel_s / 1e9 if kernel_s > 0 else 0.0
     log(f"photon cube {n}: {pr.track_steps} track-steps in {t:.3f} s, {pr.iterations} iterations")
     return {"primaries": n, "value": pr.track_steps / t, "unit": "track-steps/s",
             "step_kernels_value": pr.track_steps / kernel_s if kernel_s > 0 else None,
@@ -222,8 +230,8 @@ def run_barrel(ems, n, args, precision):
     assert (status == 0).all()
     bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
     kernel_s = st.kernel_ms / 1e3
-    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
-    achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    per_step = BYTES_PER_STEP["fp64" if precision == ems.EMS_FP64 else "mixed"]
+    achieved = per_step * pr.track_steps / kernel_s / 1e9 if kernel_s > 0 else 0.0
     log(f"barrel {n} ({'fp64' if precision == ems.EMS_FP64 else 'mixed'}): {pr.track_steps} "
         f"track-steps in {t:.3f} s, {pr.iterations} iterations")
     return {"value": pr.track_steps / t, "unit": "track-steps/s", "track_steps": pr.track_steps,
@@ -285,11 +293,12 @@ def main():
     r = run_transport(ems, wl, args.events, args, prec, args.precision)
     value = r["steps"] / r["t"]
     st = r["stats"]
-    # state read and written once per launch, plus each queued track written to and
-    # read back from its interaction queue
-    bytes_alg = BYTES_PER_TRACK * (st.tracks_in + st.tracks_out) + 2 * QUEUE_BYTES * st.queued
     kernel_s = st.kernel_ms / 1e3
-    achieved = bytes_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    iters = max(st.launches, 1)
+    # algorithmic bytes of one launch (iteration): the per-track-step figure times the
+    # track-steps the launch performs
+    bytes_alg = BYTES_PER_STEP[args.precision] * r["steps"] / iters
+    achieved = bytes_alg / (kernel_s / iters) / 1e9 if kernel_s > 0 else 0.0
     traffic = measured_traffic(args)
     out = {
         "metric": "track-steps/s (FP64 vs mixed-prec) + p50/p99 event latency, 1 MI355X",
@@ -314,8 +323,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per iteration",
-                     "measured_gbs": None if traffic is None else traffic / (kernel_s / max(st.launches, 1)) / 1e9,
-                     "algorithmic_bytes_per_iteration": bytes_alg / max(st.launches, 1),
+                     "measured_gbs": None if traffic is None else traffic / (kernel_s / iters) / 1e9,
+                     "algorithmic_bytes_per_iteration": bytes_alg,
+                     "algorithmic_bytes_per_track_step": BYTES_PER_STEP[args.precision],
+                     "track_steps_per_iteration": r["steps"] / iters,
+                     "state_bytes_per_iteration": state_bytes(st) / iters,
                      "kernel": "step kernels (k_transport + k_interact)",
                      "launches": st.launches,
                      "avg_iteration_ms": st.kernel_ms / max(st.launches, 1),

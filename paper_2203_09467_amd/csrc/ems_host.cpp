@@ -514,7 +514,7 @@ constexpr uint32_t kBoundMargin = 65536;
 constexpr uint32_t kStepsPerLaunch = 4;
 // a pool this small cannot fill the GPU: its launches are latency bound, so each
 // takes more steps per track (the tail of a run, long-lived loopers)
-constexpr uint64_t kTailTracks = 131072;
+constexpr uint64_t kTailTracks = 16384;
 constexpr uint32_t kTailStepsPerLaunch = 32;
 constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
 
