@@ -442,8 +442,8 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
   HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
                         b->energy, b->pos, b->dir, (uint32_t)n, s));
-  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, ne, x->e_in, x->scale,
-                           x->stage_out, s));
+  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, x->e_in,
+                           x->scale, x->stage_out, s));
   // primary energy per event (admission energy budget) and photons per event (pool sizes)
   std::vector<double> ev_e(ne);
   std::vector<int32_t> sp(n);

@@ -23,8 +23,8 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
                           const double* T, const double* pos, const double* dir, uint32_t n,
                           hipStream_t s);
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
-                             const double* T, uint32_t n_events, double* e_in, double* scale,
-                             double* e_row, hipStream_t s);
+                             const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
+                             double* scale, double* e_row, hipStream_t s);
 hipError_t launch_slots_reset(const Params& P, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t s);

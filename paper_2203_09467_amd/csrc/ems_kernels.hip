@@ -1557,29 +1557,41 @@ __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint
 }
 
 // Initialise the event slots of a batch: one block per event.  E_in = sum of its
-// primaries' kinetic energies; fixed-point scale 2^(61 - ceil(log2 E_in)) keeps the
-// sum of its deposits below 2^61 quanta; tallies and ledger zeroed.
+// primaries' kinetic energies.  No tally or ledger sum of the event can exceed
+// E_max = E_in + 2 m per primary positron (its annihilation releases the rest
+// energy; pairs produced later consume what their positrons release), so the
+// fixed-point scale 2^(61 - ceil(log2 E_max)) keeps every sum below 2^61 quanta.
+// Tallies and ledger zeroed.
 __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots,
-                             const double* T, double* e_in, double* scale, double* e_row) {
+                             const double* T, const int32_t* sp, double* e_in, double* scale,
+                             double* e_row) {
   const uint32_t e = blockIdx.x;
   const int64_t a = off[e], b = off[e + 1];
   __shared__ double part[kBlock];
-  double s = 0.0;
-  for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) s += T[r];
+  __shared__ double partm[kBlock];
+  double s = 0.0, sm = 0.0;
+  for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) {
+    s += T[r];
+    sm += T[r] + (sp[r] == EMS_POSITRON ? 2.0 * kMe : 0.0);
+  }
   part[threadIdx.x] = s;
+  partm[threadIdx.x] = sm;
   __syncthreads();
   for (int h = kBlock / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    if ((int)threadIdx.x < h) {
+      part[threadIdx.x] += part[threadIdx.x + h];
+      partm[threadIdx.x] += partm[threadIdx.x + h];
+    }
     __syncthreads();
   }
   const uint32_t slot = slots[e];
   for (int j = threadIdx.x; j < P.nbins; j += blockDim.x) P.tally[(size_t)slot * P.nbins + j] = 0ull;
   if (threadIdx.x < kLedger) P.ledger[(size_t)slot * kLedger + threadIdx.x] = 0ull;
   if (threadIdx.x == 0) {
-    const double E = part[0];
+    const double E = part[0], Emax = partm[0];
     int ex = 0;
-    if (E > 0.0) {
-      frexp(E, &ex);  // E < 2^ex
+    if (Emax > 0.0) {
+      frexp(Emax, &ex);  // Emax < 2^ex
     }
     e_in[slot] = E;
     e_row[e] = E;  // per batch row, read back by the host
@@ -1724,10 +1736,10 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
 }
 
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
-                             const double* T, uint32_t n_events, double* e_in, double* scale,
-                             double* e_row, hipStream_t s) {
+                             const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
+                             double* scale, double* e_row, hipStream_t s) {
   if (n_events == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_event_init, dim3(n_events), dim3(kBlock), 0, s, P, off, slots, T, e_in,
+  hipLaunchKernelGGL(k_event_init, dim3(n_events), dim3(kBlock), 0, s, P, off, slots, T, sp, e_in,
                      scale, e_row);
   return hipGetLastError();
 }
