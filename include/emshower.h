@@ -120,9 +120,9 @@ typedef struct {
   const uint32_t* event_ids; /* host, caller-chosen ids, unique among unread events */
   const int64_t* offsets;    /* host, n_events + 1 */
   const int32_t* species;    /* device, n_primaries */
-  const double* energy;      /* device, kinetic energies */
+  const double* energy;      /* device, kinetic energies, MeV, in (0, 1e5] (the tables' range) */
   const double* pos;         /* device, n_primaries x 3 (row-major) */
-  const double* dir;         /* device, n_primaries x 3, unit vectors */
+  const double* dir;         /* device, n_primaries x 3, unit vectors (|d|^2 within 1e-6 of 1) */
 } ems_event_batch;
 
 typedef struct {
@@ -183,7 +183,8 @@ ems_status init_geometry(ems_ctx* ctx, const ems_geometry* geom, void* stream);
  * stepped together (an iteration = one transport launch, in which a track takes
  * up to four steps while it neither interacts nor dies, then one interaction
  * launch; interactions that would overflow the pool are put off to a later
- * iteration, which changes no result).  EMS_E_CAPACITY if the batch does not fit
+ * iteration, which changes no result).  EMS_E_ARG (nothing submitted) for an
+ * invalid primary: species, energy, position or direction.  EMS_E_CAPACITY if the batch does not fit
  * the free event slots or the queue (nothing submitted), or if the pool can no
  * longer make progress.  progress (host) may be NULL. */
 ems_status transport_events(ems_ctx* ctx, const ems_event_batch* batch, int32_t max_iterations,

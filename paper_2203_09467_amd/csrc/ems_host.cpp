@@ -440,8 +440,11 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(x->stage_slot, slots.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
   const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
+  // validity flags of the batch's primaries: a word of the done line, unused otherwise
+  unsigned long long* bad = x->ctr + kLDone * kLineWords + 1;
+  HIP_OK(launch_zero_u64(bad, 1, s));
   HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
-                        b->energy, b->pos, b->dir, (uint32_t)n, s));
+                        b->energy, b->pos, b->dir, (uint32_t)n, bad, s));
   HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, x->e_in,
                            x->scale, x->stage_out, s));
   // primary energy per event (admission energy budget) and photons per event (pool sizes)
@@ -449,7 +452,17 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   std::vector<int32_t> sp(n);
   HIP_OK(hipMemcpyAsync(ev_e.data(), x->stage_out, ne * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(sp.data(), b->species, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  unsigned long long badw = 0;
+  HIP_OK(hipMemcpyAsync(&badw, bad, sizeof(badw), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  if (badw) {
+    std::string m = "transport_events: invalid primaries:";
+    if (badw & 1ull) m += " species not 0, 1 or 2;";
+    if (badw & 2ull) m += " kinetic energy not in (0, 1e5] MeV;";
+    if (badw & 4ull) m += " position not finite;";
+    if (badw & 8ull) m += " direction not a unit vector;";
+    return fail(EMS_E_ARG, m);
+  }
   for (uint64_t r = 0; r < n; ++r)
     if (sp[r] < 0 || sp[r] > 2) return fail(EMS_E_ARG, "transport_events: species must be 0, 1 or 2");
   x->id_to_slot.reserve(x->id_to_slot.size() + ne);

@@ -21,7 +21,7 @@ hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t
 hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, const uint32_t* slots,
                           const uint32_t* ids, uint32_t n_events, const int32_t* sp,
                           const double* T, const double* pos, const double* dir, uint32_t n,
-                          hipStream_t s);
+                          unsigned long long* bad, hipStream_t s);
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
                              const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
                              double* scale, double* e_row, hipStream_t s);

@@ -1531,11 +1531,26 @@ __global__ void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur, uint32_t
 
 // Copy a batch's primaries into the ring at tail; row r belongs to the event e with
 // off[e] <= r < off[e+1] (binary search over the staged offsets).
+// Rows that are not a valid primary set bits of *bad: 1 species, 2 kinetic energy
+// not in (0, 100 GeV], 4 position not finite, 8 direction not a finite unit vector.
 __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint32_t* slots,
                           const uint32_t* ids, uint32_t n_events, const int32_t* sp,
-                          const double* T, const double* pos, const double* dir, uint32_t n) {
+                          const double* T, const double* pos, const double* dir, uint32_t n,
+                          unsigned long long* bad) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
+  {
+    const double t = T[r], x = pos[3 * (size_t)r], y = pos[3 * (size_t)r + 1],
+                 z = pos[3 * (size_t)r + 2], u = dir[3 * (size_t)r], v = dir[3 * (size_t)r + 1],
+                 w = dir[3 * (size_t)r + 2];
+    const double d2 = u * u + v * v + w * w;
+    unsigned long long f = 0;
+    if (sp[r] < 0 || sp[r] > 2) f |= 1ull;
+    if (!(t > 0.0 && t <= 1.0e5)) f |= 2ull;
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) f |= 4ull;
+    if (!(fabs(d2 - 1.0) <= 1e-6)) f |= 8ull;
+    if (f) atomicOr(bad, f);
+  }
   uint32_t lo = 0, hi = n_events;  // find e: off[e] <= r < off[e+1]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -1728,10 +1743,10 @@ hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t
 hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, const uint32_t* slots,
                           const uint32_t* ids, uint32_t n_events, const int32_t* sp,
                           const double* T, const double* pos, const double* dir, uint32_t n,
-                          hipStream_t s) {
+                          unsigned long long* bad, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_enqueue, dim3(blocks_for(n, 256)), dim3(256), 0, s, q, tail, off, slots, ids,
-                     n_events, sp, T, pos, dir, n);
+                     n_events, sp, T, pos, dir, n, bad);
   return hipGetLastError();
 }
 

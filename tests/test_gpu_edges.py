@@ -1,8 +1,8 @@
 """Edge cases of the transport path through the C ABI, against the oracle where a
 result is computed: primaries born outside the world, primaries below the tracking
 cut (a positron there annihilates at rest), a looper cap of a few steps, empty
-and bounded calls, and the error paths (duplicate ids, invalid species, unknown
-and unfinished events) that must change no state."""
+and bounded calls, and the error paths (duplicate ids, invalid primaries, too many events,
+unknown and unfinished events) that must change no state."""
 import dataclasses
 
 import numpy as np
@@ -100,12 +100,20 @@ def test_error_paths_change_no_state():
     with pytest.raises(ems.EmsError) as e:
         ctx.transport(ems.DeviceEvents(bad), -1)
     assert e.value.status == -1
+    for sp, T, pos, d in ((W.GAMMA, 0.0, [0, 0, 0], [0, 0, 1]),            # no energy
+                          (W.ELECTRON, np.nan, [0, 0, 0], [0, 0, 1]),       # energy not finite
+                          (W.ELECTRON, 2.0e5, [0, 0, 0], [0, 0, 1]),        # above the tables
+                          (W.GAMMA, 10.0, [np.inf, 0, 0], [0, 0, 1]),       # position not finite
+                          (W.GAMMA, 10.0, [0, 0, 0], [0, 0.5, 0.5])):       # not a unit vector
+        with pytest.raises(ems.EmsError) as e:
+            ctx.transport(ems.DeviceEvents(_events([sp], [T], [pos], [d], ids=[11])), -1)
+        assert e.value.status == -1
     too_many = _events([W.ELECTRON] * 9, [1.0] * 9, [[0, 0, 0]] * 9, [[0, 0, 1]] * 9,
                        ids=np.arange(20, 29))
     with pytest.raises(ems.EmsError) as e:
         ctx.transport(ems.DeviceEvents(too_many), -1)
     assert e.value.status == -3
-    _, _, status = ctx.read(np.array([7, 9, 20, 12345], np.uint32))
+    _, _, status = ctx.read(np.array([7, 9, 11, 20, 12345], np.uint32))
     assert (status == -1).all()  # none of them was submitted
     # the context still works and gives the same tallies as a fresh one
     pr = ctx.transport(ems.DeviceEvents(wl.events), -1)
