@@ -160,10 +160,11 @@ def run_transport(ems, wl, n_events, args, precision, log_name):
                 ledger_max=float(np.abs(bal / led[:, 0]).max()))
 
 
-def run_serving(ems, args, precision):
+def run_serving(ems, args, precision, rate=None):
     from paper_2203_09467_amd.serve import serve
     import workloads as W
-    wl = W.serving(n_events=args.serve_events, rate_hz=args.serve_rate)
+    rate = args.serve_rate if rate is None else rate
+    wl = W.serving(n_events=args.serve_events, rate_hz=rate)
     ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
                       max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
                       seed=wl.seed, precision=precision, energy_budget=args.serve_budget,
@@ -173,7 +174,7 @@ def run_serving(ems, args, precision):
     ctx.close()
     e_mean = float(wl.events.energy.sum() / wl.events.n_events)
     return {"p50_ms": res["p50"] * 1e3, "p99_ms": res["p99"] * 1e3,
-            "events": wl.events.n_events, "offered_rate_hz": args.serve_rate,
+            "events": wl.events.n_events, "offered_rate_hz": rate,
             "mean_event_energy_GeV": e_mean / 1000.0,
             "track_steps_per_s": res["track_steps"] / res["wall"], "wall_s": res["wall"],
             "peak_events_in_flight": res["peak_events"]}
@@ -263,6 +264,8 @@ def main():
     ap.add_argument("--serve-budget", type=float, default=5e7,
                     help="energy in flight of the serving loop, MeV")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
+    ap.add_argument("--serve-rate-high", type=float, default=120.0,
+                    help="a second, higher offered load (events/s); 0 skips it")
     ap.add_argument("--serve-iters", type=int, default=32,
                     help="step iterations per transport call of the serving loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -347,6 +350,11 @@ def main():
                           "mixed": run_serving(ems, args, ems.EMS_MIXED),
                           "workload": "calorimeter geometry; events of U{1..500} primaries "
                                       "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
+        if args.serve_rate_high > 0:
+            r2 = args.serve_rate_high
+            out["serving"]["higher_load"] = {"offered_rate_hz": r2,
+                                             "fp64": run_serving(ems, args, ems.EMS_FP64, r2),
+                                             "mixed": run_serving(ems, args, ems.EMS_MIXED, r2)}
     if not args.no_barrel:
         fm = run_barrel(ems, args.barrel_events, args, ems.EMS_MIXED)
         fd = run_barrel(ems, args.barrel_events, args, ems.EMS_FP64)
