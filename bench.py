@@ -168,7 +168,7 @@ def run_serving(ems, args, precision, rate=None):
     ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
                       max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
                       seed=wl.seed, precision=precision, energy_budget=args.serve_budget,
-                      iterations_per_sync=min(args.per_sync, args.serve_iters))
+                      iterations_per_sync=min(args.serve_per_sync, args.serve_iters))
     ctx.setup(wl.materials, wl.options, wl.geometry)
     res = serve(ctx, wl.events, iterations=args.serve_iters, time_limit=300.0)
     ctx.close()
@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
     ap.add_argument("--serve-rate-high", type=float, default=120.0,
                     help="a second, higher offered load (events/s); 0 skips it")
+    ap.add_argument("--serve-per-sync", type=int, default=4,
+                    help="iterations per host synchronisation in the serving loop")
     ap.add_argument("--serve-iters", type=int, default=32,
                     help="step iterations per transport call of the serving loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
