@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
             "or_locate": (i, [C.c_void_p, d, d, d, d, d, d]),
             "or_distance": (d, [C.c_void_p, i, P(d), P(d), P(i)]),
             "or_step": (i, [C.c_void_p, u32, P(Track), P(StepResult)]),
+            "or_rotate": (None, [P(d), d, d, P(d)]),
             "or_field_kappa": (d, [d, d, d]),
             "or_rk4": (None, [d, d, P(d), P(d), P(d), P(d)]),
             "or_field_move": (i, [C.c_void_p, i, d, d, i, P(d), P(d), P(d), P(i)]),
@@ -305,6 +306,14 @@ class World:
         if hist is not None:
             res["esc_hist"] = hist
         return res
+
+
+def rotate(d, c, phi):
+    """The oracle's rotation of unit vector d by polar cosine c and azimuth phi."""
+    a = (C.c_double * 3)(*[float(x) for x in d])
+    o = (C.c_double * 3)()
+    lib().or_rotate(a, float(c), float(phi), o)
+    return np.array(list(o))
 
 
 def closed(name: str, *args) -> float:

@@ -158,6 +158,10 @@ void or_rk4(double kappa, double h, const double r[3], const double d[3], double
 int or_field_move(const or_world* w, int vol, double kappa, double s_max, int vacuum, double r[3],
                   double d[3], double* s_out, int* next);
 
+/* Turn unit direction d by polar cosine c and azimuth phi about itself (the rotation
+ * every interaction uses for its products); o is a unit vector. */
+void or_rotate(const double d[3], double c, double phi, double o[3]);
+
 int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result* res);
 
 typedef struct {

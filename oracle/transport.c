@@ -355,6 +355,9 @@ static void rotate(const double d[3], double c, double phi, double o[3]) {
   o[2] /= n;
 }
 
+/* Exported for the pins of the rotation (test infrastructure). */
+void or_rotate(const double d[3], double c, double phi, double o[3]) { rotate(d, c, phi, o); }
+
 /* direction of a p_a - b p_b */
 static void momentum_diff(double a, const double da[3], double b, const double db[3], double o[3]) {
   o[0] = a * da[0] - b * db[0];

@@ -145,6 +145,30 @@ def test_restricted_stopping_power_tied_to_delta_cross_section(orc, positron, T,
     assert orc.closed("scol", positron, n_el, I, T, cut) + hard == pytest.approx(unres, rel=1e-9)
 
 
+@pytest.mark.parametrize("positron", [0, 1])
+@pytest.mark.parametrize("T", [0.012, 0.3, 5.0, 200.0, 1e4])
+@pytest.mark.parametrize("I", [823e-6, 188e-6])
+def test_restricted_at_largest_cut_is_unrestricted_icru37(orc, positron, T, I):
+    """With the cut at the largest energy transfer (T/2 for e-, T for e+) the restricted
+    collision stopping power is the unrestricted ICRU 37 (Berger-Seltzer) formula, written
+    here in its own standard form:  S = 2 pi r_e^2 m n_el / beta^2 [ln(tau^2 (tau+2) / (2 I^2))
+    + F(tau)], F- = 1 - beta^2 + (tau^2/8 - (2 tau + 1) ln 2)/(tau+1)^2,
+    F+ = 2 ln 2 - beta^2/12 (23 + 14/(tau+2) + 10/(tau+2)^2 + 4/(tau+2)^3)."""
+    n_el = 2.7e24
+    tau = T / ME
+    g = tau + 1.0
+    b2 = 1.0 - 1.0 / (g * g)
+    Im = I / ME
+    if positron:
+        y = tau + 2.0
+        F = 2 * math.log(2) - b2 / 12 * (23 + 14 / y + 10 / y ** 2 + 4 / y ** 3)
+    else:
+        F = 1 - b2 + (tau * tau / 8 - (2 * tau + 1) * math.log(2)) / (g * g)
+    S = 2 * math.pi * RE ** 2 * ME * n_el / b2 * (math.log(tau * tau * (tau + 2) / (2 * Im * Im)) + F)
+    cut = T if positron else T / 2
+    assert orc.closed("scol", positron, n_el, I, T, cut) == pytest.approx(S, rel=1e-12)
+
+
 def test_stopping_power_cut_saturates(orc):
     n_el, I = 1e24, 188e-6
     T = 3.0
