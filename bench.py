@@ -1,23 +1,30 @@
 """Benchmark: electromagnetic-shower transport throughput on one MI355X.
 
-Workload (default): 1e5 primary 1 GeV electrons at normal incidence on the
+Headline workload: 1e6 primary 10 GeV electrons at normal incidence on the
 50-layer 2 mm Pb + 5 mm LAr calorimeter (40 x 40 cm), full e-/e+/photon physics,
-0.7 mm production cut, FP64, seed 2.  One benchmark "step" is the transport of
-the whole batch to completion (every step of the hot path: admission, cross
-sections, interaction lengths, step limits, boundaries, continuous loss,
-interactions, secondaries, compaction, tallies) with the primaries already
-resident in HBM.  value = track-steps / s over the timed steps.
+0.7 mm production cut, seed 3, transported in FP64 and then in mixed precision
+on identical random streams.  The primaries of the whole batch are resident in
+HBM before timing starts.  The timed steps together cover every one of the 1e6
+events: step j transports slice j of the batch to completion (every part of the
+hot path: admission, cross sections, interaction lengths, step limits,
+boundaries, continuous loss, interactions, secondaries, compaction, tallies)
+and reads its tallies back, which releases the slice's event slots for the next
+one.  Warmup steps transport slices of other event ids.  value = FP64
+track-steps / s over the timed steps; the mixed-precision rate, its per-layer
+deviation from FP64 and its speed-up are reported beside it.
 
 Also reported: the step kernels against the HBM roofline (algorithmic bytes =
 160 B per FP64 track-step -- the minimal track state read and written by a fused
 step -- times the track-steps of an iteration, divided by the step kernels'
 HIP-event duration per iteration on their launch stream; the bytes this design
 moves per iteration and the counter-measured traffic are reported beside it),
-and the CPU oracle timed on a bounded sample of the same workload on the host
-cores (cpu_baseline).
+and the CPU oracle timed on a bounded sample of the same events on the host
+cores (cpu_baseline), whose per-event tallies are compared with the GPU's.
 """
 import argparse
+import glob
 import json
+import math
 import os
 import sys
 import time
@@ -28,11 +35,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ME = 0.51099895
 BYTES_PER_TRACK = 88  # SoA state of one track: 8 doubles + 6 words
 QUEUE_BYTES = 80      # queue entry: 7 doubles + 6 words (no interaction length)
 # algorithmic bytes per track-step of a fused step with the minimal state (read +
 # write): FP64, and mixed precision with an FP32 interaction length
 BYTES_PER_STEP = {"fp64": 160, "mixed": 152}
+# the machine's CPU share for one GPU
+CPU_SHARE = 16
 
 
 def state_bytes(st):
@@ -44,62 +54,104 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _oracle_worker(args):
-    seed, lo, hi, n_events, energy = args
-    import oracle
-    import workloads as W
-    wl = W.calorimeter(n_events, energy=energy, seed=seed)
-    w = oracle.World(wl.materials, wl.options, wl.geometry)
-    ev = wl.events.subset(np.arange(lo, hi))
-    t0 = time.perf_counter()
-    r = w.run_events(wl.seed, ev)
-    return int(r["steps"].sum()), time.perf_counter() - t0
-
-
-def cpu_baseline(n_events, energy, seed, budget_s=12.0):
-    """The oracle as it stands, events split across processes on the host cores."""
-    import multiprocessing as mp
+def host_description():
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpus_visible": cores, "cpu_model": model, "logical_cpus_total": os.cpu_count()}
+
+
+def _oracle_worker(args):
+    seed, lo, hi, n_events, energy = args
+    import oracle
+    import workloads as W
+    wl = W.calorimeter(hi - lo, energy=energy, seed=seed, first_id=lo)  # events lo .. hi-1
+    w = oracle.World(wl.materials, wl.options, wl.geometry)
+    ev = wl.events
+    t0 = time.perf_counter()
+    r = w.run_events(wl.seed, ev)
+    return int(r["steps"].sum()), time.perf_counter() - t0, r["dep"], r["ledger"]
+
+
+def cpu_baseline(n_events, energy, seed, budget_s=15.0):
+    """The oracle as it stands, events split across processes on the host cores;
+    returns the rate and the per-event tallies of the sample."""
+    import multiprocessing as mp
+    host = host_description()
+    workers = max(1, min(host["cpus_visible"], CPU_SHARE))
     # calibrate on a few events, then size the sample for ~budget_s of wall time
-    steps, dt = _oracle_worker((seed, 0, 20, n_events, energy))
+    steps, dt, _, _ = _oracle_worker((seed, 0, 4, n_events, energy))
     rate1 = steps / max(dt, 1e-9)
-    per_event = steps / 20
-    n_sample = int(min(n_events, max(cores * 20, rate1 * budget_s * cores / per_event)))
-    chunks = np.linspace(0, n_sample, cores + 1).astype(int)
+    per_event = steps / 4
+    n_sample = int(min(n_events, max(workers * 4, rate1 * budget_s * workers / per_event)))
+    chunks = np.linspace(0, n_sample, workers + 1).astype(int)
     jobs = [(seed, int(a), int(b), n_events, energy) for a, b in zip(chunks[:-1], chunks[1:]) if b > a]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(len(jobs)) as pool:
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
     total = sum(r[0] for r in res)
-    return dict(value=total / wall, unit="track-steps/s", cores=len(jobs), kind="oracle",
-                sample=f"events 0..{n_sample - 1} of the benchmark batch ({total} track-steps, "
-                       f"{wall:.1f} s wall, {len(jobs)} processes)",
-                one_core_value=rate1, one_core_sample=f"events 0..19 ({steps} track-steps) in one process")
+    dep = np.concatenate([r[2] for r in res])
+    led = np.concatenate([r[3] for r in res])
+    out = dict(value=total / wall, unit="track-steps/s", cores=len(jobs), kind="oracle",
+               sample=f"events 0..{n_sample - 1} of the benchmark batch ({total} track-steps, "
+                      f"{wall:.1f} s wall, {len(jobs)} processes, one per core)",
+               one_core_value=rate1, one_core_sample=f"events 0..3 ({steps} track-steps) in one process",
+               host=host, note=f"worker count = min(visible CPUs, {CPU_SHARE}), the box's CPU share "
+                               "for one GPU")
+    return out, dep, led
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_calorimeter_fp64_traffic.json")
+def _batch_sigma(x, n_batches=20):
+    n = x.shape[0] // n_batches * n_batches
+    b = x[:n].reshape(n_batches, -1, x.shape[1]).mean(1)
+    return b.std(0, ddof=1) / math.sqrt(n_batches)
 
 
-def measured_traffic(args):
-    """HBM bytes per step iteration from the committed FETCH_SIZE / WRITE_SIZE counters
-    of the default FP64 calorimeter workload, or None when they do not apply (another
-    workload or precision, or kernel code changed since they were taken)."""
-    if args.precision != "fp64" or args.events != 100_000 or args.energy != 1000.0:
-        return None
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-        sha = kernel_source_digest(os.path.join(ROOT, t["kernel_source"]))
-        same = (sha == t["kernel_code_sha256"] and t["energy_budget_MeV"] == args.budget and
-                t["pool_slots"] == args.pool and t["iterations_per_sync"] == args.per_sync)
-    except (OSError, KeyError, ValueError):
-        return None
-    return float(t["bytes_per_iteration"]) if same else None
+def compare_layers(g, o, rel_bar):
+    """Per layer (Pb + LAr of each of the 50 layers): |mean_G - mean_O| against
+    3 sigma (batch means of both) + rel_bar |mean_O|; returns the worst ratio."""
+    lg = g.reshape(g.shape[0], -1, 2).sum(2)
+    lo = o.reshape(o.shape[0], -1, 2).sum(2)
+    sg, so = _batch_sigma(lg), _batch_sigma(lo)
+    mg, mo = lg.mean(0), lo.mean(0)
+    allowed = 3 * np.sqrt(sg ** 2 + so ** 2) + rel_bar * np.abs(mo) + 1e-300
+    ratio = np.abs(mg - mo) / allowed
+    return float(ratio.max()), bool((ratio <= 1.0).all())
+
+
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "*_traffic.json")
+
+
+def measured_traffic(args, precision=None):
+    """HBM bytes per step iteration from a committed FETCH_SIZE / WRITE_SIZE profile
+    taken with the same workload, precision and run settings, or None when none
+    applies (kernel code changed since, or other settings)."""
+    precision = precision or args.precision
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+            sha = kernel_source_digest(os.path.join(ROOT, t["kernel_source"]))
+            same = (sha == t["kernel_code_sha256"] and t["precision"] == precision and
+                    t["events"] == args.events and t["energy_MeV"] == args.energy and
+                    t["energy_budget_MeV"] == args.budget and t["pool_slots"] == args.pool and
+                    t["iterations_per_sync"] == args.per_sync)
+        except (OSError, KeyError, ValueError):
+            continue
+        if same:
+            return float(t["bytes_per_iteration"])
+    return None
 
 
 def kernel_source_digest(path):
@@ -114,50 +166,65 @@ def kernel_source_digest(path):
     return hashlib.sha256(src.encode()).hexdigest()
 
 
-def run_transport(ems, wl, n_events, args, precision, log_name):
-    """Transport the whole batch args.warmup + args.steps times; returns the timed totals."""
+def run_transport(ems, args, precision, log_name, keep):
+    """Transport the batch in args.steps timed slices after args.warmup slices of other
+    event ids; each slice runs to completion and its tallies are read (slots released)
+    inside the timed region.  Returns the timed totals, the per-layer sums over the
+    whole batch and the per-event tallies of events 0..keep-1."""
     import torch
-    n_steps = args.warmup + args.steps
-    ctx = ems.Context(pool_capacity=args.pool, max_events=n_events * n_steps,
-                      max_bins=wl.geometry.n_bins, queue_capacity=n_events, seed=wl.seed,
-                      precision=precision, energy_budget=args.budget, time_steps=True,
-                      iterations_per_sync=args.per_sync)
+    import workloads as W
+    n = args.events
+    per = -(-n // args.steps)
+    n_all = n + args.warmup * per
+    wl = W.calorimeter(n_all, energy=args.energy, seed=args.seed)
+    ctx = ems.Context(pool_capacity=args.pool, max_events=per, max_bins=wl.geometry.n_bins,
+                      queue_capacity=per, seed=wl.seed, precision=precision,
+                      energy_budget=args.budget, time_steps=True, iterations_per_sync=args.per_sync)
     ctx.setup(wl.materials, wl.options, wl.geometry)
-    batches = []
-    for j in range(n_steps):
-        ev = wl.events.subset(np.arange(n_events))
-        ev.event_ids = (np.arange(n_events) + j * n_events).astype(np.uint32)
-        batches.append(ems.DeviceEvents(ev))
+    dev = ems.DeviceEvents(wl.events)  # every primary of every slice resident in HBM
+    # warmup slices: ids n .. n_all-1; timed slices: ids 0 .. n-1
+    slices = [(n + j * per, n + (j + 1) * per) for j in range(args.warmup)]
+    slices += [(j * per, min(n, (j + 1) * per)) for j in range(args.steps)]
+    layers = np.zeros(wl.geometry.n_bins)
+    kept_dep, kept_led = [], []
+    ledger_max = 0.0
+    total_steps, iters, peak, step_s = 0, 0, 0, []
     torch.cuda.synchronize()
-    total_steps, iters, peak = 0, 0, 0
     t0 = time.perf_counter()
-    for j in range(n_steps):
+    for j, (a, b) in enumerate(slices):
         timed = j >= args.warmup
         if timed and j == args.warmup:
             ctx.step_stats(reset=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         ts = time.perf_counter()
-        pr = ctx.transport(batches[j], -1)
-        torch.cuda.synchronize()
-        log(f"{log_name} step {j} ({'timed' if timed else 'warmup'}): {pr.track_steps} track-steps "
-            f"in {time.perf_counter() - ts:.3f} s, {pr.iterations} iterations, peak pool "
+        pr = ctx.transport(dev.slice(a, b), -1)
+        dep, led, status = ctx.read(wl.events.event_ids[a:b])
+        dt = time.perf_counter() - ts
+        assert (status == 0).all() and pr.alive == 0
+        log(f"{log_name} step {j} ({'timed' if timed else 'warmup'}): events {a}..{b - 1}, "
+            f"{pr.track_steps} track-steps in {dt:.3f} s, {pr.iterations} iterations, peak pool "
             f"{pr.peak_alive}, deferred {pr.deferred}")
         if timed:
             total_steps += pr.track_steps
             iters += pr.iterations
             peak = max(peak, pr.peak_alive)
+            step_s.append(dt)
+            layers += dep.sum(0)
+            bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * ME * (led[:, 3] - led[:, 4]))
+            ledger_max = max(ledger_max, float(np.abs(bal / led[:, 0]).max()))
+            if a < keep:
+                m = min(b, keep) - a
+                kept_dep.append(dep[:m].copy())
+                kept_led.append(led[:m].copy())
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t0
     st = ctx.step_stats()
-    ids = np.concatenate([b.ids for b in batches[args.warmup:]])
-    dep, led, status = ctx.read(ids)
-    assert (status == 0).all()
-    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
-    layers = dep.reshape(len(ids), -1).sum(0)
     ctx.close()
     return dict(steps=total_steps, t=t_run, iters=iters, peak=peak, stats=st, layers=layers,
-                ledger_max=float(np.abs(bal / led[:, 0]).max()))
+                ledger_max=ledger_max, step_s=step_s, per=per,
+                kept_dep=np.concatenate(kept_dep) if kept_dep else None,
+                kept_led=np.concatenate(kept_led) if kept_led else None)
 
 
 def run_serving(ems, args, precision, rate=None):
@@ -229,7 +296,7 @@ def run_barrel(ems, n, args, precision):
     dep, led, status = ctx.read(wl.events.event_ids)
     ctx.close()
     assert (status == 0).all()
-    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * 0.51099895 * (led[:, 3] - led[:, 4]))
+    bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * ME * (led[:, 3] - led[:, 4]))
     kernel_s = st.kernel_ms / 1e3
     per_step = BYTES_PER_STEP["fp64" if precision == ems.EMS_FP64 else "mixed"]
     achieved = per_step * pr.track_steps / kernel_s / 1e9 if kernel_s > 0 else 0.0
@@ -241,13 +308,38 @@ def run_barrel(ems, n, args, precision):
             "ledger_max_rel_error": float(np.abs(bal / led[:, 0]).max())}
 
 
+def roofline(r, precision, traffic):
+    st = r["stats"]
+    kernel_s = st.kernel_ms / 1e3
+    iters = max(st.launches, 1)
+    # algorithmic bytes of one launch (iteration): the per-track-step figure times the
+    # track-steps the launch performs
+    bytes_alg = BYTES_PER_STEP[precision] * r["steps"] / iters
+    iter_s = kernel_s / iters
+    achieved = bytes_alg / iter_s / 1e9 if kernel_s > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per iteration (FETCH_SIZE + WRITE_SIZE, scaled)",
+            "measured_gbs": None if traffic is None else traffic / iter_s / 1e9,
+            "measured_frac": None if traffic is None else traffic / iter_s / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_iteration": bytes_alg,
+            "algorithmic_bytes_per_track_step": BYTES_PER_STEP[precision],
+            "track_steps_per_iteration": r["steps"] / iters,
+            "state_bytes_per_iteration": state_bytes(st) / iters,
+            "kernel": "step kernels (k_transport + k_interact), one iteration per launch pair",
+            "launches": st.launches, "avg_iteration_ms": st.kernel_ms / iters,
+            "step_kernel_share": kernel_s / r["t"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--events", type=int, default=100_000)
-    ap.add_argument("--energy", type=float, default=1000.0, help="primary energy, MeV")
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps; together they cover every event of the batch")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed slices of other event ids")
+    ap.add_argument("--events", type=int, default=1_000_000)
+    ap.add_argument("--energy", type=float, default=10_000.0, help="primary energy, MeV")
+    ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool", type=int, default=1 << 24)
     ap.add_argument("--budget", type=float, default=1e8, help="energy in flight, MeV")
@@ -275,7 +367,8 @@ def main():
                          "to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the path would "
+                                   "shard by event, one context per GPU)"}))
         sys.exit(2)
     if args.copy_calibration:
         import torch
@@ -290,21 +383,18 @@ def main():
         return
 
     import paper_2203_09467_amd as ems
-    import workloads as W
 
-    seed = 2
-    wl = W.calorimeter(args.events, energy=args.energy, seed=seed)
     prec = ems.EMS_FP64 if args.precision == "fp64" else ems.EMS_MIXED
-    r = run_transport(ems, wl, args.events, args, prec, args.precision)
+    cpu = None
+    keep = 0
+    if not args.no_cpu_baseline:
+        log("cpu baseline: timing the oracle on a sample of the batch")
+        cpu, o_dep, o_led = cpu_baseline(args.events, args.energy, args.seed)
+        keep = o_dep.shape[0]
+    r = run_transport(ems, args, prec, args.precision, keep)
     value = r["steps"] / r["t"]
-    st = r["stats"]
-    kernel_s = st.kernel_ms / 1e3
-    iters = max(st.launches, 1)
-    # algorithmic bytes of one launch (iteration): the per-track-step figure times the
-    # track-steps the launch performs
-    bytes_alg = BYTES_PER_STEP[args.precision] * r["steps"] / iters
-    achieved = bytes_alg / (kernel_s / iters) / 1e9 if kernel_s > 0 else 0.0
-    traffic = measured_traffic(args)
+    workload = (f"calorimeter: {args.events} x {args.energy / 1000:g} GeV e- on 50 x (2 mm Pb + "
+                f"5 mm LAr), 40x40 cm, 0.7 mm cut, seed {args.seed}")
     out = {
         "metric": "track-steps/s (FP64 vs mixed-prec) + p50/p99 event latency, 1 MI355X",
         "value": value,
@@ -318,34 +408,52 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == ems.EMS_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"calorimeter: {args.events} x {args.energy / 1000:g} GeV e- on "
-                               "50 x (2 mm Pb + 5 mm LAr), 40x40 cm, 0.7 mm cut, seed 2",
-                   "precision": args.precision, "pool_slots": args.pool,
+        "config": {"workload": workload, "precision": args.precision,
+                   "events_per_step": r["per"], "pool_slots": args.pool,
                    "energy_budget_MeV": args.budget, "iterations_per_sync": args.per_sync,
-                   "iterations": r["iters"],
-                   "peak_tracks_in_flight": r["peak"], "track_steps": r["steps"],
-                   "ledger_max_rel_error": r["ledger_max"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes per iteration",
-                     "measured_gbs": None if traffic is None else traffic / (kernel_s / iters) / 1e9,
-                     "algorithmic_bytes_per_iteration": bytes_alg,
-                     "algorithmic_bytes_per_track_step": BYTES_PER_STEP[args.precision],
-                     "track_steps_per_iteration": r["steps"] / iters,
-                     "state_bytes_per_iteration": state_bytes(st) / iters,
-                     "kernel": "step kernels (k_transport + k_interact)",
-                     "launches": st.launches,
-                     "avg_iteration_ms": st.kernel_ms / max(st.launches, 1),
-                     "step_kernel_share": kernel_s / r["t"]},
+                   "iterations": r["iters"], "peak_tracks_in_flight": r["peak"],
+                   "track_steps": r["steps"], "ledger_max_rel_error": r["ledger_max"],
+                   "step_ms": [round(x * 1e3, 2) for x in r["step_s"]],
+                   "step_ms_max_over_min": max(r["step_s"]) / min(r["step_s"])},
+        "roofline": roofline(r, args.precision, measured_traffic(args)),
     }
+    if cpu is not None:
+        n = min(keep, r["kept_dep"].shape[0])
+        g, o = r["kept_dep"][:n], o_dep[:n]
+        e_in = o_led[:n, 0]
+        match = np.abs(g - o).max(1) <= 1e-9 * e_in
+        worst, ok = compare_layers(g, o, 1e-3 if prec == ems.EMS_FP64 else 5e-3)
+        cpu["parity_vs_gpu"] = {
+            "events": n, "precision": args.precision,
+            "events_equal_to_1e-9_E_in": float(match.mean()),
+            "per_layer_worst_ratio_to_bar": worst, "per_layer_within_bar": ok,
+            "bar": "3 sigma (batch means) + 0.1 % per layer" if prec == ems.EMS_FP64 else
+                   "3 sigma (batch means) + 0.5 % per layer"}
     if args.precision == "fp64" and not args.no_mixed:
-        m = run_transport(ems, wl, args.events, args, ems.EMS_MIXED, "mixed")
+        m = run_transport(ems, args, ems.EMS_MIXED, "mixed", keep)
         big = r["layers"] >= 0.01 * r["layers"].sum()
         rel = np.abs(m["layers"] - r["layers"])[big] / r["layers"][big]
+        lf = r["layers"].reshape(-1, 2).sum(1)
+        lm = m["layers"].reshape(-1, 2).sum(1)
+        bigl = lf >= 0.01 * lf.sum()
+        rel_l = np.abs(lm - lf)[bigl] / lf[bigl]
         out["mixed"] = {"value": m["steps"] / m["t"], "unit": "track-steps/s",
                         "speedup_vs_fp64": (m["steps"] / m["t"]) / value,
+                        "ms_per_step": m["t"] / args.steps * 1e3,
+                        "max_rel_dev_per_layer_vs_fp64": float(rel_l.max()),
                         "max_rel_dev_per_bin_vs_fp64": float(rel.max()),
-                        "ledger_max_rel_error": m["ledger_max"]}
+                        "layers_compared": int(bigl.sum()),
+                        "note": "paired on identical Philox streams over every event of the batch; "
+                                "layers (Pb + LAr) and bins holding >= 1 % of the deposit",
+                        "ledger_max_rel_error": m["ledger_max"],
+                        "step_ms_max_over_min": max(m["step_s"]) / min(m["step_s"]),
+                        "roofline": roofline(m, "mixed", measured_traffic(args, "mixed"))}
+        if cpu is not None:
+            n = min(keep, m["kept_dep"].shape[0])
+            worst, ok = compare_layers(m["kept_dep"][:n], o_dep[:n], 5e-3)
+            out["mixed"]["vs_oracle"] = {"events": n, "per_layer_worst_ratio_to_bar": worst,
+                                         "per_layer_within_bar": ok,
+                                         "bar": "3 sigma (batch means) + 0.5 % per layer"}
     if not args.no_serving:
         log("serving: Poisson arrivals, FP64 then mixed")
         out["serving"] = {"fp64": run_serving(ems, args, ems.EMS_FP64),
@@ -369,9 +477,8 @@ def main():
         out["photon_cube_sat"] = {
             "workload": "10 MeV photons into a 10 cm Pb cube, one photon per event, FP64",
             "runs": [run_photon_sat(ems, n, args) for n in (1_000_000, 10_000_000)]}
-    if not args.no_cpu_baseline:
-        log("cpu baseline: timing the oracle on a sample of the batch")
-        out["cpu_baseline"] = cpu_baseline(args.events, args.energy, seed)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

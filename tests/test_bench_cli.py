@@ -8,6 +8,8 @@ import subprocess
 import sys
 import types
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -26,15 +28,33 @@ def _bench():
     return m
 
 
-def test_traffic_applies_only_to_its_settings():
+def test_traffic_applies_only_to_its_settings(tmp_path, monkeypatch):
     b = _bench()
-    with open(b.TRAFFIC_FILE) as f:
-        t = json.load(f)
-    base = dict(precision="fp64", events=100_000, energy=1000.0, budget=t["energy_budget_MeV"],
-                pool=t["pool_slots"], per_sync=t["iterations_per_sync"])
-    assert b.measured_traffic(types.SimpleNamespace(**base)) == t["bytes_per_iteration"]
-    for k, v in (("precision", "mixed"), ("events", 1000), ("budget", 1.0), ("per_sync", 1)):
+    src = tmp_path / "k.hip"
+    src.write_text("int k() { return 1; }\n")
+    t = {"kernel_source": str(src), "kernel_code_sha256": b.kernel_source_digest(str(src)),
+         "precision": "fp64", "events": 1000, "energy_MeV": 10000.0, "energy_budget_MeV": 1e8,
+         "pool_slots": 1 << 24, "iterations_per_sync": 4, "bytes_per_iteration": 123.0}
+    (tmp_path / "w_traffic.json").write_text(json.dumps(t))
+    monkeypatch.setattr(b, "TRAFFIC_GLOB", str(tmp_path / "*_traffic.json"))
+    base = dict(precision="fp64", events=1000, energy=10000.0, budget=1e8, pool=1 << 24, per_sync=4)
+    assert b.measured_traffic(types.SimpleNamespace(**base)) == 123.0
+    for k, v in (("precision", "mixed"), ("events", 10), ("energy", 1.0), ("budget", 1.0),
+                 ("per_sync", 1), ("pool", 64)):
         assert b.measured_traffic(types.SimpleNamespace(**{**base, k: v})) is None
+    src.write_text("int k() { return 2; }\n")  # the kernel code changed since
+    assert b.measured_traffic(types.SimpleNamespace(**base)) is None
+
+
+def test_layer_comparison_bar():
+    b = _bench()
+    rng = np.random.default_rng(0)
+    o = rng.normal(10.0, 1.0, (400, 100))
+    g = o + rng.normal(0, 1e-3, o.shape)
+    worst, ok = b.compare_layers(g, o, 1e-3)
+    assert ok and worst < 1
+    worst, ok = b.compare_layers(g * 1.05, o, 1e-3)  # 5 % too high everywhere
+    assert not ok and worst > 1
 
 
 def test_kernel_digest_ignores_comments(tmp_path):
