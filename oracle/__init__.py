@@ -38,7 +38,9 @@ class Geometry(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_vol", C.c_int), ("bounds", C.POINTER(C.c_double)),
                 ("material", C.POINTER(C.c_int)), ("tally_bin", C.POINTER(C.c_int)),
                 ("n_bins", C.c_int), ("half_x", C.c_double), ("half_y", C.c_double),
-                ("half_z", C.c_double), ("bz", C.c_double), ("field_tol", C.c_double)]
+                ("half_z", C.c_double), ("bz", C.c_double), ("field_tol", C.c_double),
+                ("n_surf", C.c_int), ("surf", C.POINTER(C.c_double)),
+                ("face_off", C.POINTER(C.c_int)), ("faces", C.POINTER(C.c_int))]
 
 
 class Track(C.Structure):
@@ -104,6 +106,8 @@ def lib() -> C.CDLL:
             "or_distance": (d, [C.c_void_p, i, P(d), P(d), P(i)]),
             "or_step": (i, [C.c_void_p, u32, P(Track), P(StepResult)]),
             "or_rotate": (None, [P(d), d, d, P(d)]),
+            "or_csg_side": (i, [P(d), P(d), P(d)]),
+            "or_csg_exit": (d, [P(d), P(d), P(d), i]),
             "or_field_kappa": (d, [d, d, d]),
             "or_rk4": (None, [d, d, P(d), P(d), P(d), P(d)]),
             "or_field_move": (i, [C.c_void_p, i, d, d, i, P(d), P(d), P(d), P(i)]),
@@ -193,6 +197,14 @@ class World:
                      _ptr(self._mat, C.c_int), _ptr(self._bin, C.c_int), int(geometry.n_bins),
                      float(geometry.half_x), float(geometry.half_y), float(geometry.half_z),
                      float(geometry.bz), float(geometry.field_tol))
+        if getattr(geometry, "surfaces", None) is not None:
+            self._surf = np.ascontiguousarray(geometry.surfaces, np.float64).reshape(-1)
+            self._foff = np.ascontiguousarray(geometry.face_off, np.int32)
+            self._faces = np.ascontiguousarray(geometry.faces, np.int32)
+            g.n_surf = self._surf.shape[0] // 10
+            g.surf = _ptr(self._surf, C.c_double)
+            g.face_off = _ptr(self._foff, C.c_int)
+            g.faces = _ptr(self._faces, C.c_int)
         self.options = options
         self.geometry = geometry
         self.n_bins = int(geometry.n_bins)
@@ -306,6 +318,18 @@ class World:
         if hist is not None:
             res["esc_hist"] = hist
         return res
+
+
+def csg_side(q, p, d) -> int:
+    """Side (+1 / -1) of quadric surface q (10 coefficients) at p moving along d."""
+    a = lambda v: (C.c_double * len(v))(*[float(x) for x in v])
+    return lib().or_csg_side(a(q), a(p), a(d))
+
+
+def csg_exit(q, p, d, sigma: int) -> float:
+    """Distance along d from p to where quadric q leaves side sigma (inf: never)."""
+    a = lambda v: (C.c_double * len(v))(*[float(x) for x in v])
+    return lib().or_csg_exit(a(q), a(p), a(d), int(sigma))
 
 
 def rotate(d, c, phi):

@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.c", "physics.c", "transport.c", "field.c"]
+SOURCES = ["philox.c", "physics.c", "transport.c", "field.c", "csg.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

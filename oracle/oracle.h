@@ -36,7 +36,7 @@ extern "C" {
 
 enum { OR_GAMMA = 0, OR_ELECTRON = 1, OR_POSITRON = 2 };
 enum { OR_NGRID = 200, OR_NQ = 4, OR_MAXMAT = 8 };
-enum { OR_GEOM_SLABS = 0, OR_GEOM_CYLINDERS = 1 };
+enum { OR_GEOM_SLABS = 0, OR_GEOM_CYLINDERS = 1, OR_GEOM_CSG = 2 };
 enum { OR_OUTSIDE = -1 };
 enum { OR_LIM_GEO = 0, OR_LIM_PHYS = 1, OR_LIM_CONT = 2, OR_LIM_LOOPER = 3 };
 
@@ -66,6 +66,11 @@ typedef struct {
   double half_z;         /* cylinders: half length */
   double bz;             /* uniform field along z, tesla (cylinders only) */
   double field_tol;      /* cm: RK4 local error tolerance */
+  /* OR_GEOM_CSG: cells (the volumes) as intersections of quadric half-spaces */
+  int n_surf;
+  const double* surf;    /* n_surf x 10: qxx qyy qzz qxy qyz qzx px py pz k */
+  const int* face_off;   /* n_vol + 1: faces of cell k are face_off[k] .. face_off[k+1]-1 */
+  const int* faces;      /* surface index * 2 + (1 if the cell is on the side f > 0) */
 } or_geometry;
 
 typedef struct {
@@ -149,6 +154,11 @@ double or_material_X0(const or_world* w, int mat);
 int or_locate(const or_world* w, double x, double y, double z, double u, double v, double wz);
 double or_distance(const or_world* w, int vol, const double pos[3], const double dir[3],
                    int* next);
+
+/* Quadric-surface cells (csg.c): side of a surface (+1 / -1) at p moving along d,
+ * and the distance along d to where f leaves side sigma (HUGE_VAL: never). */
+int or_csg_side(const double* q, const double p[3], const double d[3]);
+double or_csg_exit(const double* q, const double p[3], const double d[3], int sigma);
 
 /* Charged tracks in the uniform field B_z: curvature, one RK4 step, and the curved
  * move of a step (returns 0 at s_max, 1 at a boundary, 2 for a looper). */

@@ -21,6 +21,10 @@ typedef struct {
   int* material;
   int* bin;
   double hx, hy, hz, bz, tol;
+  int n_surf;
+  double* surf;   /* CSG: n_surf x 10 quadric coefficients */
+  int* face_off;  /* CSG: n_vol + 1 */
+  int* faces;     /* CSG: surface * 2 + (cell on the f > 0 side) */
 } or_geom_data;
 
 struct or_world {
@@ -37,5 +41,7 @@ double or_interp_ln(const or_world* w, const double* v, double lnT);
 double or_inverse_ln(const or_world* w, const double* v, double r);
 int or_geometry_init(or_world* w, const or_geometry* g);
 void or_geometry_free(or_world* w);
+int or_csg_locate(const or_geom_data* g, const double p[3], const double d[3]);
+double or_csg_distance(const or_geom_data* g, int k, const double p[3], const double d[3], int* next);
 
 #endif

@@ -38,11 +38,28 @@ int or_geometry_init(or_world* w, const or_geometry* g) {
   d->kind = g->kind;
   d->n_vol = g->n_vol;
   d->n_bins = g->n_bins;
+  if (g->kind == OR_GEOM_CSG) {
+    if (g->n_surf < 1 || !g->surf || !g->face_off || !g->faces || g->face_off[0] != 0) return -1;
+    const int nf = g->face_off[g->n_vol];
+    d->n_surf = g->n_surf;
+    d->surf = (double*)malloc(sizeof(double) * 10 * (size_t)g->n_surf);
+    d->face_off = (int*)malloc(sizeof(int) * (size_t)(g->n_vol + 1));
+    d->faces = (int*)malloc(sizeof(int) * (size_t)(nf > 0 ? nf : 1));
+    if (!d->surf || !d->face_off || !d->faces) return -1;
+    memcpy(d->surf, g->surf, sizeof(double) * 10 * (size_t)g->n_surf);
+    memcpy(d->face_off, g->face_off, sizeof(int) * (size_t)(g->n_vol + 1));
+    memcpy(d->faces, g->faces, sizeof(int) * (size_t)nf);
+    for (int k = 0; k < g->n_vol; ++k)
+      if (g->face_off[k + 1] < g->face_off[k]) return -1;
+    for (int j = 0; j < nf; ++j)
+      if (g->faces[j] < 0 || (g->faces[j] >> 1) >= g->n_surf) return -1;
+  }
   d->bounds = (double*)malloc(sizeof(double) * (size_t)(g->n_vol + 1));
   d->material = (int*)malloc(sizeof(int) * (size_t)g->n_vol);
   d->bin = (int*)malloc(sizeof(int) * (size_t)g->n_vol);
   if (!d->bounds || !d->material || !d->bin) return -1;
-  memcpy(d->bounds, g->bounds, sizeof(double) * (size_t)(g->n_vol + 1));
+  if (g->bounds) memcpy(d->bounds, g->bounds, sizeof(double) * (size_t)(g->n_vol + 1));
+  else memset(d->bounds, 0, sizeof(double) * (size_t)(g->n_vol + 1));
   memcpy(d->material, g->material, sizeof(int) * (size_t)g->n_vol);
   memcpy(d->bin, g->tally_bin, sizeof(int) * (size_t)g->n_vol);
   for (int i = 0; i < g->n_vol; ++i)
@@ -59,11 +76,18 @@ void or_geometry_free(or_world* w) {
   free(w->geo.bounds);
   free(w->geo.material);
   free(w->geo.bin);
+  free(w->geo.surf);
+  free(w->geo.face_off);
+  free(w->geo.faces);
 }
 
 /* Volume containing the point; on a surface the direction decides. */
 int or_locate(const or_world* w, double x, double y, double z, double u, double v, double wz) {
   const or_geom_data* g = &w->geo;
+  if (g->kind == OR_GEOM_CSG) {
+    const double p[3] = {x, y, z}, d[3] = {u, v, wz};
+    return or_csg_locate(g, p, d);
+  }
   if (g->kind == OR_GEOM_SLABS) {
     if (fabs(x) > g->hx || fabs(y) > g->hy) return OR_OUTSIDE;
     for (int j = 0; j < g->n_vol; ++j) {
@@ -92,6 +116,7 @@ double or_distance(const or_world* w, int vol, const double p[3], const double d
   const double INF = HUGE_VAL;
   double s = INF;
   int nx = OR_OUTSIDE;
+  if (g->kind == OR_GEOM_CSG) return or_csg_distance(g, vol, p, d, next);
   if (g->kind == OR_GEOM_SLABS) {
     if (d[2] > 0.0) {
       s = (g->bounds[vol + 1] - p[2]) / d[2];

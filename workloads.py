@@ -35,6 +35,9 @@ GAMMA, ELECTRON, POSITRON = 0, 1, 2
 LEAD = (82.0, 207.2, 11.35, 823.0e-6)
 LIQUID_ARGON = (18.0, 39.948, 1.396, 188.0e-6)
 SILICON = (14.0, 28.0855, 2.33, 173.0e-6)
+IRON = (26.0, 55.845, 7.874, 286.0e-6)
+COPPER = (29.0, 63.546, 8.96, 322.0e-6)
+TUNGSTEN = (74.0, 183.84, 19.3, 727.0e-6)
 
 TRACKING_CUT = 0.01  # 10 keV
 
@@ -58,8 +61,8 @@ class Options:
 
 @dataclasses.dataclass
 class Geometry:
-    kind: int  # 0 slabs (z planes), 1 cylinders (radii)
-    bounds: np.ndarray  # n_vol + 1 float64
+    kind: int  # 0 slabs (z planes), 1 cylinders (radii), 2 quadric-surface cells
+    bounds: np.ndarray  # n_vol + 1 float64 (kind 0, 1)
     material: np.ndarray  # n_vol int32 (-1 vacuum)
     tally_bin: np.ndarray  # n_vol int32
     n_bins: int
@@ -68,6 +71,13 @@ class Geometry:
     half_z: float = 0.0
     bz: float = 0.0
     field_tol: float = 1.0e-5
+    # kind 2: surfaces (n_surf x 10 coefficients of
+    #   qxx x^2 + qyy y^2 + qzz z^2 + qxy xy + qyz yz + qzx zx + px x + py y + pz z + k)
+    # and the faces of each cell: cell k has faces[face_off[k]:face_off[k+1]], each
+    # surface * 2 + (1 if the cell lies where f > 0, 0 where f < 0)
+    surfaces: Optional[np.ndarray] = None
+    face_off: Optional[np.ndarray] = None
+    faces: Optional[np.ndarray] = None
 
     @property
     def n_vol(self) -> int:
@@ -160,6 +170,128 @@ def calorimeter(n_events: int = 100_000, energy: float = 1000.0, seed: int = 2,
                                 first_id)
     return Workload("calorimeter", [LEAD, LIQUID_ARGON], opts, geom, ev, seed,
                     f"{n_events} x {energy / 1000:g} GeV e- on 50 x (2 mm Pb + 5 mm LAr)")
+
+
+def material_stack(n_events: int = 200, energy: float = 1000.0, seed: int = 6) -> Workload:
+    """Six materials in turn (Pb, Fe, Cu, Si, LAr, W), 30 slabs of 4 mm, 40 x 40 cm;
+    electrons at normal incidence from the origin, calorimeter physics.  In FP64 the
+    charged-particle tables of six materials (6 x 2 x 200 x 4 doubles = 76.8 KB)
+    exceed the 64 KB per-block staging budget of the step kernels, so this workload
+    runs their global-memory variant."""
+    n_slab = 30
+    bounds = np.arange(n_slab + 1, dtype=np.float64) * 0.4
+    mat = (np.arange(n_slab) % 6).astype(np.int32)
+    geom = Geometry(0, bounds, mat, np.arange(n_slab, dtype=np.int32), n_slab, half_x=20.0,
+                    half_y=20.0)
+    ev = _single_primary_events(n_events, ELECTRON, energy, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    return Workload("material_stack", [LEAD, IRON, COPPER, SILICON, LIQUID_ARGON, TUNGSTEN],
+                    Options(production_cut=0.07), geom, ev, seed,
+                    f"{n_events} x {energy / 1000:g} GeV e- on 30 slabs of six materials")
+
+
+# ---- quadric surfaces (coefficients only) and cells built from them
+def plane(axis: int, at: float) -> np.ndarray:
+    """f = x_axis - at."""
+    q = np.zeros(10)
+    q[6 + axis] = 1.0
+    q[9] = -at
+    return q
+
+
+def sphere(r: float, center=(0.0, 0.0, 0.0)) -> np.ndarray:
+    cx, cy, cz = center
+    return np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0, -2 * cx, -2 * cy, -2 * cz,
+                     cx * cx + cy * cy + cz * cz - r * r])
+
+
+def cylinder(axis: int, r: float) -> np.ndarray:
+    """Infinite circular cylinder of radius r about a coordinate axis through the origin."""
+    q = np.zeros(10)
+    for a in range(3):
+        if a != axis:
+            q[a] = 1.0
+    q[9] = -r * r
+    return q
+
+
+def cone_z(slope: float) -> np.ndarray:
+    """x^2 + y^2 - (slope z)^2: both nappes of a cone about z with its apex at the origin."""
+    return np.array([1.0, 1.0, -slope * slope, 0, 0, 0, 0, 0, 0, 0.0])
+
+
+def _cells(cells):
+    """cells: list of lists of (surface, sense) with sense -1 (f < 0) or +1 (f > 0)."""
+    off = np.zeros(len(cells) + 1, np.int32)
+    faces = []
+    for k, c in enumerate(cells):
+        faces += [2 * s + (1 if sense > 0 else 0) for s, sense in c]
+        off[k + 1] = len(faces)
+    return off, np.array(faces, np.int32)
+
+
+def calorimeter_csg(n_layers: int = 50, pb: float = 0.2, lar: float = 0.5,
+                    half_xy: float = 20.0) -> Geometry:
+    """The slab calorimeter written as quadric-surface cells: every Pb or LAr slab is
+    the cell between two z planes and the four lateral walls.  Faces are listed
+    y walls, x walls, then z planes, so that ties go to the walls (y before x) as
+    in the slab navigation."""
+    slab = calorimeter_geometry(n_layers, pb, lar, half_xy)
+    b = slab.bounds
+    surf = [plane(1, -half_xy), plane(1, half_xy), plane(0, -half_xy), plane(0, half_xy)]
+    surf += [plane(2, z) for z in b]
+    cells = [[(0, 1), (1, -1), (2, 1), (3, -1), (4 + i, 1), (5 + i, -1)] for i in range(len(b) - 1)]
+    off, faces = _cells(cells)
+    return Geometry(2, np.zeros(len(b)), slab.material.copy(), slab.tally_bin.copy(), slab.n_bins,
+                    surfaces=np.array(surf), face_off=off, faces=faces)
+
+
+def csg_module_geometry() -> Geometry:
+    """A 40 cm cube of lead holding a silicon spherical shell (8 < r < 10 cm) around
+    liquid argon, in which a tungsten rod (radius 3 cm along x, |x| < 6 cm) sits at
+    the centre; a conical vacuum channel (x^2 + y^2 < (0.3 z)^2) runs from the face
+    z = -20 cm to z = -10 cm.  Spheres, an x-cylinder, a cone and planes; every cell
+    is an intersection of half-spaces."""
+    surf = [plane(0, -20.0), plane(0, 20.0), plane(1, -20.0), plane(1, 20.0), plane(2, -20.0),
+            plane(2, 20.0),                 # 0-5 faces of the cube
+            sphere(10.0), sphere(8.0),      # 6, 7
+            cylinder(0, 3.0),               # 8
+            plane(0, -6.0), plane(0, 6.0),  # 9, 10
+            plane(2, -10.0),                # 11
+            cone_z(0.3)]                    # 12
+    box_sides = [(0, 1), (1, -1), (2, 1), (3, -1)]
+    cells = [
+        [(8, -1), (9, 1), (10, -1)],                             # 0 tungsten rod
+        [(7, -1), (9, 1), (10, -1), (8, 1)],                     # 1 LAr around the rod
+        [(7, -1), (9, -1)],                                      # 2 LAr, x < -6
+        [(7, -1), (10, 1)],                                      # 3 LAr, x > 6
+        [(6, -1), (7, 1)],                                       # 4 Si shell
+        box_sides + [(5, -1), (11, 1), (6, 1)],                  # 5 Pb above z = -10
+        box_sides + [(4, 1), (11, -1), (12, 1)],                 # 6 Pb below, outside the cone
+        box_sides + [(4, 1), (11, -1), (12, -1)],                # 7 vacuum channel
+    ]
+    off, faces = _cells(cells)
+    material = np.array([3, 1, 1, 1, 2, 0, 0, -1], np.int32)
+    return Geometry(2, np.zeros(len(cells) + 1), material, np.arange(len(cells), dtype=np.int32),
+                    len(cells), surfaces=np.array(surf), face_off=off, faces=faces)
+
+
+def csg_module(n_events: int = 1000, seed: int = 7, source_seed: int = 70) -> Workload:
+    """Point source at the centre of the quadric-cell module: one primary per event,
+    60/20/20 % e-/e+/photon, log-uniform 0.1-10 GeV, isotropic."""
+    rng = np.random.default_rng(source_seed)
+    n = n_events
+    u = rng.random(n)
+    species = np.where(u < 0.6, ELECTRON, np.where(u < 0.8, POSITRON, GAMMA)).astype(np.int32)
+    energy = _log_uniform(rng, n, 100.0, 10000.0)
+    cost = 2.0 * rng.random(n) - 1.0
+    phi = 2.0 * np.pi * rng.random(n)
+    sint = np.sqrt(1.0 - cost * cost)
+    d = np.stack([sint * np.cos(phi), sint * np.sin(phi), cost], axis=1)
+    ev = Events(np.arange(n, dtype=np.uint32), np.arange(n + 1, dtype=np.int64), species, energy,
+                np.zeros((n, 3)), d)
+    return Workload("csg_module", [LEAD, LIQUID_ARGON, SILICON, TUNGSTEN],
+                    Options(production_cut=0.07), csg_module_geometry(), ev, seed,
+                    f"{n} primaries 0.1-10 GeV from the centre of a quadric-cell module")
 
 
 def barrel_geometry() -> Geometry:
