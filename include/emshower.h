@@ -25,8 +25,9 @@
  *  - Streams: `stream` is a hipStream_t (NULL = default stream); all device
  *    work of a call is enqueued on it.  Calls on one context must not overlap.
  *  - Errors: no exception crosses the ABI.  A negative status means the call
- *    changed no state; ems_last_error() gives a message (thread-local).
- *    EMS_NOT_READY (1) means "try later", not an error.
+ *    changed no state -- except EMS_E_STALLED, see transport_events --;
+ *    ems_last_error() gives a message (thread-local).  EMS_NOT_READY (1) means
+ *    "try later", not an error.
  */
 #ifndef EMSHOWER_H
 #define EMSHOWER_H
@@ -47,12 +48,14 @@ typedef enum {
   EMS_E_STATE = -2,    /* call out of order (tables before geometry before transport) */
   EMS_E_CAPACITY = -3, /* workspace, event slots, pending queue or pool exhausted */
   EMS_E_HIP = -4,      /* HIP runtime error */
-  EMS_E_INTERNAL = -5
+  EMS_E_INTERNAL = -5,
+  EMS_E_STALLED = -6   /* the track pool cannot progress (see transport_events); the
+                          batch of the call was accepted and stays submitted */
 } ems_status;
 
 typedef enum { EMS_FP64 = 0, EMS_MIXED = 1 } ems_precision;
 typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_species;
-typedef enum { EMS_GEOM_SLABS = 0, EMS_GEOM_CYLINDERS = 1 } ems_geometry_kind;
+typedef enum { EMS_GEOM_SLABS = 0, EMS_GEOM_CYLINDERS = 1, EMS_GEOM_CSG = 2 } ems_geometry_kind;
 
 /* Sizes fixed at creation. */
 typedef struct {
@@ -67,10 +70,15 @@ typedef struct {
   uint32_t iterations_per_sync; /* step iterations enqueued per host synchronisation
                                    (admission and completion bookkeeping happen at
                                    synchronisations); 0 = 8, at most 32 */
+  uint32_t spill_capacity;  /* tracks that may wait in pinned host memory when the pool
+                               runs full (88 B each, allocated by ems_create); 0 = none */
 } ems_config;
 
 /* flags: time every step-kernel launch with HIP events on the launch stream */
 #define EMS_FLAG_TIME_STEPS 1u
+/* flags: keep an escape spectrum per event (3 species x 200 log-energy bins of the
+ * table grid, 4.8 KB of workspace per event slot, twice), read by tally_read */
+#define EMS_FLAG_EVENT_ESCAPE 2u
 
 /* Step-kernel statistics accumulated since creation or the last reset. */
 typedef struct {
@@ -99,12 +107,24 @@ typedef struct {
   uint32_t max_steps;     /* per-track step cap (loopers); energy goes to "killed" */
 } ems_physics_options;
 
-/* Volumes are slabs between z-planes (lateral walls |x| <= half_x, |y| <= half_y)
- * or shells between radii (|z| <= half_z), listed inside-out / front-to-back. */
+/* Volumes are slabs between z-planes (lateral walls |x| <= half_x, |y| <= half_y),
+ * shells between radii (|z| <= half_z), listed inside-out / front-to-back, or
+ * quadric-surface cells (paper Sec. 2.3 "Geometry and EM fields": the ORANGE
+ * model of cells bounded by quadric surfaces, one level): each cell is the
+ * intersection of half-spaces f_s < 0 or f_s > 0 of surfaces
+ *   f(x) = qxx x^2 + qyy y^2 + qzz z^2 + qxy xy + qyz yz + qzx zx + px x + py y + pz z + k,
+ * and a point outside every cell is outside the world.  A track leaves its cell
+ * at the nearest root, over the cell's faces, where f turns to the other side
+ * (the first face listed wins ties); it enters the first cell (in index order)
+ * that has the crossed surface on the other side and whose remaining faces hold
+ * at the crossing point, else the first other cell without the crossed surface
+ * on the side left that holds it, else it escapes.  On a surface, the direction
+ * of motion decides the side.  Cells must not overlap. */
 typedef struct {
   int32_t kind;              /* ems_geometry_kind */
-  int32_t n_vol;
-  const double* bounds;      /* host, n_vol + 1 increasing planes or radii */
+  int32_t n_vol;             /* volumes (cells) */
+  const double* bounds;      /* host, n_vol + 1 increasing planes or radii (ignored for
+                                EMS_GEOM_CSG) */
   const int32_t* material;   /* host, n_vol material indices (-1 = vacuum) */
   const int32_t* tally_bin;  /* host, n_vol bins in [0, n_bins) */
   int32_t n_bins;
@@ -112,6 +132,12 @@ typedef struct {
   double bz;                 /* uniform field along z, tesla (charged tracks follow RK4
                                 substeps; 0 = straight lines) */
   double field_tol;          /* cm: RK4 position error and boundary sagitta tolerance */
+  /* EMS_GEOM_CSG only (else ignored): */
+  int32_t n_surf;            /* surfaces, 1 .. 4096 */
+  const double* surfaces;    /* host, n_surf x 10: qxx qyy qzz qxy qyz qzx px py pz k */
+  const int32_t* face_off;   /* host, n_vol + 1: cell k has faces face_off[k] .. face_off[k+1]-1
+                                (at most 32768 faces in all) */
+  const int32_t* faces;      /* host: surface * 2 + (1 if the cell lies where f > 0) */
 } ems_geometry;
 
 /* Primaries of a batch of events; rows of event e are offsets[e] .. offsets[e+1]-1. */
@@ -134,7 +160,21 @@ typedef struct {
   uint64_t deferred;         /* interactions put off for lack of pool room (the track
                                 returns to the pool and does it in a later iteration) */
   uint64_t peak_alive;       /* largest pool occupancy seen by this call */
+  uint64_t spilled;          /* tracks waiting in host memory after the call */
+  uint64_t spilled_total;    /* tracks moved to host memory by this call */
 } ems_progress;
+
+/* One step iteration of a transport_events call (paper Sec. 3.2, "Preliminary
+ * results": tracks in flight and queued per step iteration, and the time each
+ * iteration takes). */
+typedef struct {
+  uint32_t photons, charged; /* tracks in the pool when the iteration starts */
+  uint32_t interactions;     /* tracks queued for an interaction, put-off ones included */
+  uint32_t tracks_out;       /* tracks in the pool after the iteration */
+  uint64_t waiting_primaries;/* primaries queued for admission (at the sync interval start) */
+  uint64_t spilled;          /* tracks waiting in host memory (at the sync interval start) */
+  double ms;                 /* step-kernel time of the iteration (EMS_FLAG_TIME_STEPS), else 0 */
+} ems_iteration_record;
 
 /* Per-track single-step record (diagnostics and parity tests). */
 typedef struct {
@@ -158,7 +198,12 @@ typedef struct {
 size_t ems_workspace_bytes(const ems_config* cfg);
 
 /* Carve the caller's device workspace (>= ems_workspace_bytes(cfg) bytes, 256-byte
- * aligned) into the pool, tables, tallies and queues.  *out owns no device memory. */
+ * aligned) into the pool, tables, tallies and queues.  *out owns no device memory.
+ * Paper Sec. 2.1 ("Code Architecture"): immutable parameter data (tables, geometry)
+ * kept apart from per-track state, and secondaries reserved in a large device array
+ * of fixed capacity; here every such array is sized once, from cfg, and lives in
+ * the one workspace.  EMS_E_ARG for an invalid cfg or a misaligned workspace,
+ * EMS_E_CAPACITY for a workspace smaller than needed. */
 ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, ems_ctx** out);
 void ems_destroy(ems_ctx* ctx);
 const char* ems_last_error(void);
@@ -178,29 +223,53 @@ ems_status init_geometry(ems_ctx* ctx, const ems_geometry* geom, void* stream);
 
 /* Submit a batch (may be NULL or empty) to the pending queue, then run up to
  * max_iterations step iterations (< 0: until every submitted event is done).
- * Events are admitted whole, in submission order, while pool slots and the
- * energy budget allow; tracks of all admitted events share the pool and are
- * stepped together (an iteration = one transport launch, in which a track takes
- * up to four steps while it neither interacts nor dies, then one interaction
- * launch; interactions that would overflow the pool are put off to a later
- * iteration, which changes no result).  EMS_E_ARG (nothing submitted) for an
- * invalid primary: species, energy, position or direction.  EMS_E_CAPACITY if the batch does not fit
- * the free event slots or the queue (nothing submitted), or if the pool can no
- * longer make progress.  progress (host) may be NULL. */
+ * Paper Sec. 2.4 ("User-interface and I/O"): the device is used best with many
+ * events in flight at once; Sec. 3.2 ("Preliminary results"): a step iteration is
+ * several kernels with synchronisation points, run until the tracks of the
+ * events drain.  Events are admitted whole, in submission order, while pool slots
+ * and the energy budget allow; tracks of all admitted events share the pool and
+ * are stepped together (an iteration = one transport launch, in which a track
+ * takes up to four steps while it neither interacts nor dies, then one
+ * interaction launch; interactions that would overflow the pool are put off to a
+ * later iteration, which changes no result).  Calls may be bounded and repeated
+ * (serving): the state of events in flight stays on the device between calls.
+ * Errors: EMS_E_ARG (nothing submitted) for an invalid primary: species, energy,
+ * position or direction, or a duplicate event id.  EMS_E_CAPACITY (nothing
+ * submitted) if the batch does not fit the free event slots or the queue.
+ * EMS_E_STALLED if the pool is full of interactions put off for lack of room, so
+ * that no track can step: the batch stays submitted and every event stays in
+ * flight; the context can still be read and destroyed.  progress (host) may be
+ * NULL. */
 ems_status transport_events(ems_ctx* ctx, const ems_event_batch* batch, int32_t max_iterations,
                             void* stream, ems_progress* progress);
 
-/* Read finished events: dep (host, n x n_bins) energy per tally bin, ledger
- * (host, n x 5: primary energy, escaped kinetic energy, killed energy, pair
- * conversions, annihilations), status (host, n): EMS_OK, EMS_NOT_READY (still in
- * flight) or EMS_E_ARG (unknown id).  A read event's slot is released.
- * Returns EMS_OK if every id was read. */
+/* Read finished events (paper Sec. 2.4: scoring regions declared by the client,
+ * tallied in kernel code on the device and processed on the host):
+ *   dep (host, n x n_bins): energy deposited per tally bin;
+ *   ledger (host, n x 5): primary kinetic energy, escaped kinetic energy, killed
+ *     energy, pair conversions, annihilations;
+ *   steps (host, n x 3, or NULL): track-steps of photons, electrons, positrons;
+ *   esc_hist (host, n x 3 x 200, or NULL; needs EMS_FLAG_EVENT_ESCAPE, else
+ *     EMS_E_STATE): escaping tracks by species and log-energy bin of the grid;
+ *   status (host, n): EMS_OK, EMS_NOT_READY (still in flight) or EMS_E_ARG
+ *     (unknown id, or an id repeated in this call: only its first entry is read).
+ * Rows whose status is not EMS_OK are left untouched.  A read event's slot is
+ * released.  Returns EMS_OK if every id was read, EMS_NOT_READY otherwise;
+ * EMS_E_HIP releases nothing. */
 ems_status tally_read(ems_ctx* ctx, uint32_t n, const uint32_t* event_ids, double* dep,
-                      double* ledger, int32_t* status, void* stream);
+                      double* ledger, uint64_t* steps, uint64_t* esc_hist, int32_t* status,
+                      void* stream);
 
 /* Run-level counters: steps (host, 3) track-steps by species, esc_hist (host,
  * 3 x 200 or NULL) escaping tracks by species and log-energy bin of the grid. */
 ems_status ems_run_counters(ems_ctx* ctx, uint64_t* steps, uint64_t* esc_hist, void* stream);
+
+/* The iterations recorded since creation or the last reset (the first 2^20 of them;
+ * iterations with an empty pool are not recorded): *n = how many; the first
+ * min(*n, max) are copied to out (host, may be NULL when max = 0).  reset != 0
+ * clears the record after reading. */
+ems_status ems_iteration_log(ems_ctx* ctx, ems_iteration_record* out, uint64_t max, uint64_t* n,
+                             int32_t reset);
 
 /* Step-kernel statistics of the context (host *out); reset != 0 zeroes them after
  * reading. */

@@ -33,8 +33,10 @@ _lib = C.CDLL(LIB_PATH)
 
 EMS_OK, EMS_NOT_READY = 0, 1
 EMS_FP64, EMS_MIXED = 0, 1
+EMS_E_ARG, EMS_E_STATE, EMS_E_CAPACITY, EMS_E_HIP, EMS_E_INTERNAL, EMS_E_STALLED = -1, -2, -3, -4, -5, -6
 STATUS = {0: "EMS_OK", 1: "EMS_NOT_READY", -1: "EMS_E_ARG", -2: "EMS_E_STATE",
-          -3: "EMS_E_CAPACITY", -4: "EMS_E_HIP", -5: "EMS_E_INTERNAL"}
+          -3: "EMS_E_CAPACITY", -4: "EMS_E_HIP", -5: "EMS_E_INTERNAL", -6: "EMS_E_STALLED"}
+EMS_FLAG_TIME_STEPS, EMS_FLAG_EVENT_ESCAPE = 1, 2
 NGRID = 200
 
 
@@ -49,7 +51,7 @@ class Config(C.Structure):
     _fields_ = [("pool_capacity", C.c_uint32), ("max_events", C.c_uint32),
                 ("max_bins", C.c_uint32), ("queue_capacity", C.c_uint32), ("seed", C.c_uint32),
                 ("precision", C.c_int), ("energy_budget", C.c_double), ("flags", C.c_uint32),
-                ("iterations_per_sync", C.c_uint32)]
+                ("iterations_per_sync", C.c_uint32), ("spill_capacity", C.c_uint32)]
 
 
 class KernelStats(C.Structure):
@@ -75,7 +77,9 @@ class Geometry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_vol", C.c_int32), ("bounds", C.POINTER(C.c_double)),
                 ("material", C.POINTER(C.c_int32)), ("tally_bin", C.POINTER(C.c_int32)),
                 ("n_bins", C.c_int32), ("half_x", C.c_double), ("half_y", C.c_double),
-                ("half_z", C.c_double), ("bz", C.c_double), ("field_tol", C.c_double)]
+                ("half_z", C.c_double), ("bz", C.c_double), ("field_tol", C.c_double),
+                ("n_surf", C.c_int32), ("surfaces", C.POINTER(C.c_double)),
+                ("face_off", C.POINTER(C.c_int32)), ("faces", C.POINTER(C.c_int32))]
 
 
 class EventBatch(C.Structure):
@@ -88,7 +92,19 @@ class Progress(C.Structure):
     _fields_ = [("alive", C.c_uint64), ("queued_primaries", C.c_uint64),
                 ("queued_events", C.c_uint64), ("iterations", C.c_uint64),
                 ("track_steps", C.c_uint64), ("deferred", C.c_uint64),
-                ("peak_alive", C.c_uint64)]
+                ("peak_alive", C.c_uint64), ("spilled", C.c_uint64),
+                ("spilled_total", C.c_uint64)]
+
+
+class IterationRecord(C.Structure):
+    _fields_ = [("photons", C.c_uint32), ("charged", C.c_uint32), ("interactions", C.c_uint32),
+                ("tracks_out", C.c_uint32), ("waiting_primaries", C.c_uint64),
+                ("spilled", C.c_uint64), ("ms", C.c_double)]
+
+
+ITERATION_DTYPE = np.dtype([("photons", "u4"), ("charged", "u4"), ("interactions", "u4"),
+                            ("tracks_out", "u4"), ("waiting_primaries", "u8"), ("spilled", "u8"),
+                            ("ms", "f8")])
 
 
 class StepRecord(C.Structure):
@@ -111,6 +127,7 @@ RECORD_DTYPE = np.dtype([("dep", "f8"), ("esc", "f8"), ("killed", "f8"), ("step_
                          ("limiter", "i4"), ("process", "i4"), ("n_pair", "i4"),
                          ("n_annih", "i4"), ("n_out", "i4"), ("escaped", "i4")])
 assert RECORD_DTYPE.itemsize == C.sizeof(StepRecord)
+assert ITERATION_DTYPE.itemsize == C.sizeof(IterationRecord)
 
 _P = C.POINTER
 _sigs = {
@@ -124,9 +141,11 @@ _sigs = {
     "transport_events": (C.c_int, [C.c_void_p, _P(EventBatch), C.c_int32, C.c_void_p,
                                    _P(Progress)]),
     "tally_read": (C.c_int, [C.c_void_p, C.c_uint32, _P(C.c_uint32), _P(C.c_double),
-                             _P(C.c_double), _P(C.c_int32), C.c_void_p]),
+                             _P(C.c_double), _P(C.c_uint64), _P(C.c_uint64), _P(C.c_int32),
+                             C.c_void_p]),
     "ems_run_counters": (C.c_int, [C.c_void_p, _P(C.c_uint64), _P(C.c_uint64), C.c_void_p]),
     "ems_step_stats": (C.c_int, [C.c_void_p, _P(KernelStats), C.c_int32]),
+    "ems_iteration_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, _P(C.c_uint64), C.c_int32]),
     "ems_step_once": (C.c_int, [C.c_void_p, _P(TrackSoA), C.c_uint32, C.c_void_p, _P(TrackSoA),
                                 _P(C.c_uint32), C.c_void_p]),
 }
@@ -182,7 +201,18 @@ def init_geometry(ctx, geometry, stream=None):
                  _np_ptr(t, C.c_int32), int(geometry.n_bins), float(geometry.half_x),
                  float(geometry.half_y), float(geometry.half_z), float(geometry.bz),
                  float(geometry.field_tol))
+    keep = []
+    if getattr(geometry, "surfaces", None) is not None:
+        sf = np.ascontiguousarray(geometry.surfaces, np.float64).reshape(-1)
+        fo = np.ascontiguousarray(geometry.face_off, np.int32)
+        fc = np.ascontiguousarray(geometry.faces, np.int32)
+        keep = [sf, fo, fc]
+        g.n_surf = sf.shape[0] // 10
+        g.surfaces = _np_ptr(sf, C.c_double)
+        g.face_off = _np_ptr(fo, C.c_int32)
+        g.faces = _np_ptr(fc, C.c_int32)
     _check(_lib.init_geometry(ctx, C.byref(g), _stream(stream)), "init_geometry")
+    del keep
 
 
 def transport_events(ctx, batch: Optional["DeviceEvents"], max_iterations: int = -1,
@@ -197,16 +227,29 @@ def transport_events(ctx, batch: Optional["DeviceEvents"], max_iterations: int =
     return pr
 
 
-def tally_read(ctx, event_ids, n_bins: int, stream=None):
+def tally_read(ctx, event_ids, n_bins: int, stream=None, steps: bool = False,
+               escape: bool = False):
+    """Returns (dep, ledger, status), followed by the per-event track-steps by species
+    (n x 3) if `steps` and the per-event escape spectra (n x 3 x 200) if `escape`."""
     ids = np.ascontiguousarray(event_ids, np.uint32)
     n = ids.shape[0]
     dep = np.zeros((n, n_bins), np.float64)
     ledger = np.zeros((n, 5), np.float64)
     status = np.zeros(n, np.int32)
+    st = np.zeros((n, 3), np.uint64) if steps else None
+    esc = np.zeros((n, 3, NGRID), np.uint64) if escape else None
     _check(_lib.tally_read(ctx, n, _np_ptr(ids, C.c_uint32), _np_ptr(dep, C.c_double),
-                           _np_ptr(ledger, C.c_double), _np_ptr(status, C.c_int32),
-                           _stream(stream)), "tally_read", ok=(EMS_OK, EMS_NOT_READY))
-    return dep, ledger, status
+                           _np_ptr(ledger, C.c_double),
+                           None if st is None else _np_ptr(st, C.c_uint64),
+                           None if esc is None else _np_ptr(esc, C.c_uint64),
+                           _np_ptr(status, C.c_int32), _stream(stream)),
+           "tally_read", ok=(EMS_OK, EMS_NOT_READY))
+    out = (dep, ledger, status)
+    if steps:
+        out += (st,)
+    if escape:
+        out += (esc,)
+    return out
 
 
 def run_counters(ctx, stream=None):
@@ -272,10 +315,12 @@ class Context:
 
     def __init__(self, pool_capacity=1 << 20, max_events=1024, max_bins=128,
                  queue_capacity=1 << 20, seed=1, precision=EMS_FP64, energy_budget=0.0,
-                 time_steps=False, iterations_per_sync=0, device="cuda"):
+                 time_steps=False, iterations_per_sync=0, event_escape=False, spill_capacity=0,
+                 device="cuda"):
         import torch
+        flags = (EMS_FLAG_TIME_STEPS if time_steps else 0) | (EMS_FLAG_EVENT_ESCAPE if event_escape else 0)
         self.cfg = Config(pool_capacity, max_events, max_bins, queue_capacity, seed, precision,
-                          energy_budget, 1 if time_steps else 0, iterations_per_sync)
+                          energy_budget, flags, iterations_per_sync, spill_capacity)
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise EmsError(-1, "ems_workspace_bytes")
@@ -304,11 +349,20 @@ class Context:
     def transport(self, batch=None, max_iterations=-1, stream=None) -> Progress:
         return transport_events(self.h, batch, max_iterations, stream)
 
-    def read(self, event_ids, stream=None):
-        return tally_read(self.h, event_ids, self.n_bins, stream)
+    def read(self, event_ids, stream=None, steps=False, escape=False):
+        return tally_read(self.h, event_ids, self.n_bins, stream, steps, escape)
 
     def counters(self, stream=None):
         return run_counters(self.h, stream)
+
+    def iteration_log(self, reset=False) -> np.ndarray:
+        """Per-iteration records (numpy structured array, ITERATION_DTYPE)."""
+        n = C.c_uint64()
+        _check(_lib.ems_iteration_log(self.h, None, 0, C.byref(n), 0), "ems_iteration_log")
+        out = np.zeros(n.value, ITERATION_DTYPE)
+        _check(_lib.ems_iteration_log(self.h, C.c_void_p(out.ctypes.data), n.value, C.byref(n),
+                                      1 if reset else 0), "ems_iteration_log")
+        return out[:n.value]
 
     def step_stats(self, reset=False) -> KernelStats:
         st = KernelStats()

@@ -15,7 +15,13 @@ namespace ems {
 constexpr int kGrid = 200;            // nodes of the log energy grid, 1 keV .. 100 GeV
 constexpr int kQ = 4;                 // quantities per (material, species, node)
 constexpr int kMaxMat = 8;
-constexpr int kLedger = 4;            // escaped (fixed point), killed (fixed point), pairs, annihilations
+// per-event ledger words: escaped (fixed point), killed (fixed point), pair conversions,
+// annihilations, track-steps of photons, electrons, positrons, one spare word
+constexpr int kLedger = 8;
+constexpr int kLedgerSteps = 4;       // first of the three track-step words
+// doubles per event row gathered for tally_read after the deposits: E_in, escaped,
+// killed, pairs, annihilations, track-steps of photons, electrons, positrons
+constexpr uint32_t kRowLedger = 8;
 constexpr uint32_t kVolOut = 0x3FFFFFFu;  // meta volume of a primary that starts outside
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
@@ -108,6 +114,15 @@ struct Params {
   const int* vmat;
   const int* vbin;
   double hx, hy, hz, bz, ftol;
+  // quadric-surface cells (gkind == EMS_GEOM_CSG): surface coefficients (10 each),
+  // the faces of each cell (surface * 2 + side), and per face code the cells that
+  // have it, in increasing order (the candidates entered through that face)
+  int n_surf;
+  const double* surf;
+  const int* face_off;
+  const int* faces;
+  const int* cand_off;
+  const int* cand;
   uint32_t seed;
   // tallies (per event slot) and run counters
   unsigned long long* tally;     // [slot][nbins], fixed point
@@ -116,7 +131,8 @@ struct Params {
   const double* scale;           // [slot] fixed-point scale 2^s
   uint32_t* done;                // [slot] list of finished slots (append)
   unsigned long long* ctr;       // kNumLines x kLineWords iteration counters
-  unsigned long long* esc_hist;  // [3][kGrid]
+  unsigned long long* esc_hist;  // [3][kGrid] escaping tracks of the run
+  unsigned long long* ev_esc;    // [slot][3][kGrid] escaping tracks per event, or null
 };
 
 // Pending primaries (ring of queue_capacity entries).

@@ -19,7 +19,6 @@
 #include <cstring>
 #include <deque>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "emshower.h"
@@ -47,6 +46,8 @@ ems_status fail(ems_status s, const std::string& msg) {
 constexpr size_t kAlign = 256;
 constexpr int kMaxPerSync = 32;
 constexpr uint32_t kMaxVol = 4096;
+constexpr uint32_t kMaxSurf = 4096;
+constexpr uint32_t kMaxFaces = 32768;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -66,6 +67,60 @@ struct EventInfo {
   uint32_t slot;
   uint32_t n_prim, n_gamma;  // primaries, of which photons
   double e_in;
+};
+
+// Event id -> slot of the unread events: open addressing with linear probing over a
+// power-of-two table holding slot + 1 (0 = empty); the id of a slot is looked up in
+// the context's slot_id.  Erasing shifts the entries of the probe run back, so the
+// table needs no tombstones.
+struct IdMap {
+  std::vector<uint32_t> t;
+  uint32_t mask = 0;
+  void init(uint32_t max_events) {
+    uint32_t c = 16;
+    while (c < 2u * max_events) c <<= 1;
+    t.assign(c, 0u);
+    mask = c - 1;
+  }
+  void clear() { std::fill(t.begin(), t.end(), 0u); }
+  uint32_t home(uint32_t id) const {
+    return (uint32_t)(((uint64_t)id * 0x9E3779B97F4A7C15ull) >> 32) & mask;
+  }
+  // slot of id, or -1
+  int64_t find(uint32_t id, const std::vector<uint32_t>& slot_id) const {
+    for (uint32_t h = home(id);; h = (h + 1) & mask) {
+      const uint32_t v = t[h];
+      if (v == 0) return -1;
+      if (slot_id[v - 1] == id) return (int64_t)(v - 1);
+    }
+  }
+  // false if id is present already (slot_id[slot] must already hold id)
+  bool insert(uint32_t id, uint32_t slot, const std::vector<uint32_t>& slot_id) {
+    for (uint32_t h = home(id);; h = (h + 1) & mask) {
+      const uint32_t v = t[h];
+      if (v == 0) {
+        t[h] = slot + 1;
+        return true;
+      }
+      if (v - 1 != slot && slot_id[v - 1] == id) return false;
+    }
+  }
+  void erase(uint32_t id, const std::vector<uint32_t>& slot_id) {
+    uint32_t h = home(id);
+    while (t[h] != 0 && slot_id[t[h] - 1] != id) h = (h + 1) & mask;
+    if (t[h] == 0) return;
+    uint32_t hole = h;
+    for (uint32_t j = (h + 1) & mask; t[j] != 0; j = (j + 1) & mask) {
+      const uint32_t k = home(slot_id[t[j] - 1]);
+      // move t[j] into the hole unless its home lies cyclically in (hole, j]
+      const bool stays = hole <= j ? (k > hole && k <= j) : (k > hole || k <= j);
+      if (!stays) {
+        t[hole] = t[j];
+        hole = j;
+      }
+    }
+    t[hole] = 0;
+  }
 };
 
 }  // namespace
@@ -90,24 +145,38 @@ struct ems_ctx {
   double* e_in = nullptr;
   double* scale = nullptr;
   int64_t* stage_off = nullptr;
+  uint32_t* stage_ng = nullptr;  // photons per event of a submitted batch
   uint32_t* stage_slot = nullptr;
   uint32_t* stage_id = nullptr;
   double* stage_out = nullptr;
+  unsigned long long* stage_esc = nullptr;  // per-event escape spectra read back, or null
   unsigned long long* ctr = nullptr;
-  // pinned host mirror of the counters and done list
+  // host mirror of the counters and done list: pinned, or in the vectors below
+  bool pinned = true;
+  std::vector<unsigned long long> h_ctr_buf;
+  std::vector<uint32_t> h_done_buf;
   unsigned long long* h_ctr = nullptr;
   uint64_t run_steps[3] = {0, 0, 0};  // track-steps by species since init_geometry
   uint32_t* h_done = nullptr;
   // event slots
   std::vector<uint32_t> free_slots;
-  std::vector<int> slot_state;  // 0 free, 1 queued or in flight, 2 finished
+  std::vector<int> slot_state;  // 0 free, 1 queued or in flight, 2 finished, 3 being read
   std::vector<uint32_t> slot_id;
   std::vector<double> slot_e;
-  std::unordered_map<uint32_t, uint32_t> id_to_slot;
+  IdMap id_to_slot;
   std::deque<EventInfo> pending;
   uint32_t q_head = 0, q_count = 0;
   uint64_t pending_prims = 0;
   double e_flight = 0.0;
+  // tracks waiting in pinned host memory: a stack of SoA rows [0, spill_top)
+  Pool hs{};
+  void* hs_block = nullptr;
+  uint64_t spill_top = 0;
+  unsigned long long* spill_hist = nullptr;  // device, kGrid
+  uint32_t* spill_cnt = nullptr;             // device, 4
+  // per-iteration records: device staging of one interval, host log
+  uint32_t* iter_log = nullptr;
+  std::vector<ems_iteration_record> log;
   // step-kernel statistics
   hipEvent_t ev[2 * kMaxPerSync] = {};
   int per_sync = 8;  // iterations per host synchronisation
@@ -156,6 +225,11 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   double* gb = c.take<double>(kMaxVol + 1);
   int* gm = c.take<int>(kMaxVol);
   int* gbin = c.take<int>(kMaxVol);
+  double* gsurf = c.take<double>((size_t)kMaxSurf * 10);
+  int* gfoff = c.take<int>(kMaxVol + 1);
+  int* gfaces = c.take<int>(kMaxFaces);
+  int* gcoff = c.take<int>(2 * kMaxSurf + 1);
+  int* gcand = c.take<int>(kMaxFaces);
   unsigned long long* tally = c.take<unsigned long long>(E * B);
   unsigned long long* ledger = c.take<unsigned long long>(E * kLedger);
   int* alive = c.take<int>(E);
@@ -164,6 +238,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   uint32_t* done = c.take<uint32_t>(E);
   unsigned long long* ctr = c.take<unsigned long long>(kNumLines * kLineWords);
   unsigned long long* esc = c.take<unsigned long long>(3 * kGrid);
+  const bool ev_esc_on = (cfg.flags & EMS_FLAG_EVENT_ESCAPE) != 0;
+  unsigned long long* ev_esc = ev_esc_on ? c.take<unsigned long long>(E * 3 * kGrid) : nullptr;
+  unsigned long long* stage_esc = ev_esc_on ? c.take<unsigned long long>(E * 3 * kGrid) : nullptr;
   Queue q;
   q.species = c.take<int32_t>(Qc);
   q.T = c.take<double>(Qc);
@@ -178,9 +255,13 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   q.event_id = c.take<uint32_t>(Qc);
   q.capacity = (uint32_t)Qc;
   int64_t* so = c.take<int64_t>(E + 1);
+  uint32_t* ilog = c.take<uint32_t>(4 * kMaxPerSync);
+  unsigned long long* sh = c.take<unsigned long long>(kGrid);
+  uint32_t* sc = c.take<uint32_t>(4);
+  uint32_t* sg = c.take<uint32_t>(E);
   uint32_t* ss = c.take<uint32_t>(E);
   uint32_t* si = c.take<uint32_t>(E);
-  double* sout = c.take<double>(E * (B + 5));
+  double* sout = c.take<double>(E * (B + kRowLedger));
   if (!x) return;
   x->set = set;
   for (int cl = 0; cl < 2; ++cl)
@@ -214,6 +295,11 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->P.bounds = gb;
   x->P.vmat = gm;
   x->P.vbin = gbin;
+  x->P.surf = gsurf;
+  x->P.face_off = gfoff;
+  x->P.faces = gfaces;
+  x->P.cand_off = gcoff;
+  x->P.cand = gcand;
   x->P.tally = tally;
   x->P.ledger = ledger;
   x->P.alive = alive;
@@ -221,20 +307,32 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->P.done = done;
   x->P.ctr = ctr;
   x->P.esc_hist = esc;
+  x->P.ev_esc = ev_esc;
+  x->stage_esc = stage_esc;
   x->scale = scale;
   x->e_in = e_in;
   x->ctr = ctr;
   x->q = q;
+  x->iter_log = ilog;
+  x->spill_hist = sh;
+  x->spill_cnt = sc;
   x->stage_off = so;
+  x->stage_ng = sg;
   x->stage_slot = ss;
   x->stage_id = si;
   x->stage_out = sout;
 }
 
+// Per-event score indices must fit the 28 index bits of the kernels' score keys.
 bool config_ok(const ems_config* c) {
-  return c && c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && c->max_events >= 1 &&
-         c->max_bins >= 1 && (uint64_t)c->max_events * c->max_bins < (1ull << 29) &&
-         c->queue_capacity >= 1 && c->iterations_per_sync <= kMaxPerSync &&
+  if (!c) return false;
+  const uint64_t E = c->max_events;
+  const bool ev_esc = (c->flags & EMS_FLAG_EVENT_ESCAPE) != 0;
+  return c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && E >= 1 && E < (1u << 26) &&
+         c->max_bins >= 1 && E * c->max_bins < (1ull << 28) &&
+         (!ev_esc || E * 3 * kGrid < (1ull << 28)) && c->queue_capacity >= 1 &&
+         c->iterations_per_sync <= kMaxPerSync &&
+         (c->flags & ~(EMS_FLAG_TIME_STEPS | EMS_FLAG_EVENT_ESCAPE)) == 0 &&
          (c->precision == EMS_FP64 || c->precision == EMS_MIXED);
 }
 
@@ -245,7 +343,7 @@ void reset_events(ems_ctx* x) {
   x->slot_state.assign(E, 0);
   x->slot_id.assign(E, 0);
   x->slot_e.assign(E, 0.0);
-  x->id_to_slot.clear();
+  x->id_to_slot.init(E);
   x->pending.clear();
   x->q_head = 0;
   x->q_count = 0;
@@ -253,9 +351,133 @@ void reset_events(ems_ctx* x) {
   x->e_flight = 0.0;
   x->nG = x->nC = 0;
   x->cur = 0;
+  x->spill_top = 0;
+}
+
+// Bytes of pinned host memory per spilled track (the SoA state of Pool without src).
+constexpr size_t kHostTrackBytes = 8 * sizeof(double) + 6 * sizeof(uint32_t);
+
+void carve_host(ems_ctx* x, uint64_t cap) {
+  char* b = static_cast<char*>(x->hs_block);
+  auto take = [&](size_t elem) {
+    char* p = b;
+    b += cap * elem;
+    return p;
+  };
+  Pool& h = x->hs;
+  h.x = reinterpret_cast<double*>(take(8));
+  h.y = reinterpret_cast<double*>(take(8));
+  h.z = reinterpret_cast<double*>(take(8));
+  h.u = reinterpret_cast<double*>(take(8));
+  h.v = reinterpret_cast<double*>(take(8));
+  h.w = reinterpret_cast<double*>(take(8));
+  h.T = reinterpret_cast<double*>(take(8));
+  h.nlam = reinterpret_cast<double*>(take(8));
+  h.k0 = reinterpret_cast<uint32_t*>(take(4));
+  h.k1 = reinterpret_cast<uint32_t*>(take(4));
+  h.k2 = reinterpret_cast<uint32_t*>(take(4));
+  h.evt = reinterpret_cast<uint32_t*>(take(4));
+  h.nstep = reinterpret_cast<uint32_t*>(take(4));
+  h.meta = reinterpret_cast<uint32_t*>(take(4));
+  h.src = nullptr;
+}
+
+// Copy n track rows between a device pool view (from row d) and the host stack
+// (from row h), in the direction `kind`.
+hipError_t copy_rows(const Pool& dev, size_t d, const Pool& host, size_t h, size_t n,
+                     hipMemcpyKind kind, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const bool up = kind == hipMemcpyHostToDevice;
+#define EMS_COPY_FIELD(f)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = up ? hipMemcpyAsync(dev.f + d, host.f + h, n * sizeof(*dev.f), kind, s)  \
+                       : hipMemcpyAsync(host.f + h, dev.f + d, n * sizeof(*dev.f), kind, s); \
+    if (e_ != hipSuccess) return e_;                                                         \
+  } while (0)
+  EMS_COPY_FIELD(x);
+  EMS_COPY_FIELD(y);
+  EMS_COPY_FIELD(z);
+  EMS_COPY_FIELD(u);
+  EMS_COPY_FIELD(v);
+  EMS_COPY_FIELD(w);
+  EMS_COPY_FIELD(T);
+  EMS_COPY_FIELD(nlam);
+  EMS_COPY_FIELD(k0);
+  EMS_COPY_FIELD(k1);
+  EMS_COPY_FIELD(k2);
+  EMS_COPY_FIELD(evt);
+  EMS_COPY_FIELD(nstep);
+  EMS_COPY_FIELD(meta);
+#undef EMS_COPY_FIELD
+  return hipSuccess;
 }
 
 }  // namespace
+
+namespace ems {
+
+ems_status fail_status(ems_status s, const std::string& msg) { return fail(s, msg); }
+
+// Context over a device workspace.  pinned: counter readbacks go to pinned host
+// memory and the optional spill buffer and step timers are allowed; otherwise the
+// context uses plain host memory for readbacks and refuses both, so that creating
+// it calls no allocating HIP routine.
+ems_status create_context(const ems_config* cfg, void* d_workspace, size_t bytes, bool pinned,
+                          const char* who, ems_ctx** out) {
+  const std::string w = who;
+  if (!out) return fail(EMS_E_ARG, w + ": out is null");
+  *out = nullptr;
+  if (!config_ok(cfg)) return fail(EMS_E_ARG, w + ": invalid configuration");
+  if (!pinned && (cfg->spill_capacity > 0 || (cfg->flags & EMS_FLAG_TIME_STEPS)))
+    return fail(EMS_E_ARG, w + ": spill_capacity and EMS_FLAG_TIME_STEPS need ems_create");
+  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+    return fail(EMS_E_ARG, w + ": workspace must be non-null and 256-byte aligned");
+  const size_t need = ems_workspace_bytes(cfg);
+  if (bytes < need)
+    return fail(EMS_E_CAPACITY, w + ": workspace of " + std::to_string(bytes) + " bytes, need " +
+                                    std::to_string(need));
+  ems_ctx* x = new (std::nothrow) ems_ctx();
+  if (!x) return fail(EMS_E_INTERNAL, w + ": out of host memory");
+  x->cfg = *cfg;
+  x->pinned = pinned;
+  Carver c{static_cast<char*>(d_workspace)};
+  carve(c, *cfg, x);
+  x->P.seed = cfg->seed;
+  x->P.max_events = cfg->max_events;
+  if (pinned) {
+    hipError_t e = hipHostMalloc((void**)&x->h_ctr, kNumLines * kLineWords * sizeof(unsigned long long),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
+                        hipHostMallocDefault);
+    if (e == hipSuccess && cfg->spill_capacity > 0) {
+      e = hipHostMalloc(&x->hs_block, (size_t)cfg->spill_capacity * kHostTrackBytes, hipHostMallocDefault);
+      if (e == hipSuccess) carve_host(x, cfg->spill_capacity);
+    }
+    if (e != hipSuccess) {
+      ems_destroy(x);
+      return fail(EMS_E_HIP, w + ": pinned host buffer: " + hipGetErrorString(e));
+    }
+  } else {
+    x->h_ctr_buf.assign((size_t)kNumLines * kLineWords, 0ull);
+    x->h_done_buf.assign(cfg->max_events, 0u);
+    x->h_ctr = x->h_ctr_buf.data();
+    x->h_done = x->h_done_buf.data();
+  }
+  x->per_sync = cfg->iterations_per_sync == 0 ? 8 : (int)cfg->iterations_per_sync;
+  if (cfg->flags & EMS_FLAG_TIME_STEPS) {
+    for (int j = 0; j < 2 * x->per_sync; ++j)
+      if (hipEventCreate(&x->ev[j]) != hipSuccess) {
+        ems_destroy(x);
+        return fail(EMS_E_HIP, w + ": hipEventCreate failed");
+      }
+  }
+  reset_events(x);
+  *out = x;
+  return EMS_OK;
+}
+
+}  // namespace ems
 
 extern "C" {
 
@@ -269,49 +491,16 @@ size_t ems_workspace_bytes(const ems_config* cfg) {
 }
 
 ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, ems_ctx** out) {
-  if (!out) return fail(EMS_E_ARG, "ems_create: out is null");
-  *out = nullptr;
-  if (!config_ok(cfg)) return fail(EMS_E_ARG, "ems_create: invalid configuration");
-  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
-    return fail(EMS_E_ARG, "ems_create: workspace must be non-null and 256-byte aligned");
-  const size_t need = ems_workspace_bytes(cfg);
-  if (bytes < need)
-    return fail(EMS_E_CAPACITY, "ems_create: workspace of " + std::to_string(bytes) +
-                                    " bytes, need " + std::to_string(need));
-  ems_ctx* x = new (std::nothrow) ems_ctx();
-  if (!x) return fail(EMS_E_INTERNAL, "ems_create: out of host memory");
-  x->cfg = *cfg;
-  Carver c{static_cast<char*>(d_workspace)};
-  carve(c, *cfg, x);
-  x->P.seed = cfg->seed;
-  x->P.max_events = cfg->max_events;
-  hipError_t e = hipHostMalloc((void**)&x->h_ctr, kNumLines * kLineWords * sizeof(unsigned long long),
-                               hipHostMallocDefault);
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
-                      hipHostMallocDefault);
-  if (e != hipSuccess) {
-    if (x->h_ctr) (void)hipHostFree(x->h_ctr);
-    delete x;
-    return fail(EMS_E_HIP, std::string("ems_create: pinned host buffer: ") + hipGetErrorString(e));
-  }
-  x->per_sync = cfg->iterations_per_sync == 0 ? 8 : (int)cfg->iterations_per_sync;
-  if (cfg->flags & EMS_FLAG_TIME_STEPS) {
-    for (int j = 0; j < 2 * x->per_sync; ++j)
-      if (hipEventCreate(&x->ev[j]) != hipSuccess) {
-        ems_destroy(x);
-        return fail(EMS_E_HIP, "ems_create: hipEventCreate failed");
-      }
-  }
-  reset_events(x);
-  *out = x;
-  return EMS_OK;
+  return ems::create_context(cfg, d_workspace, bytes, true, "ems_create", out);
 }
 
 void ems_destroy(ems_ctx* x) {
   if (!x) return;
-  if (x->h_ctr) (void)hipHostFree(x->h_ctr);
-  if (x->h_done) (void)hipHostFree(x->h_done);
+  if (x->pinned) {
+    if (x->h_ctr) (void)hipHostFree(x->h_ctr);
+    if (x->h_done) (void)hipHostFree(x->h_done);
+    if (x->hs_block) (void)hipHostFree(x->hs_block);
+  }
   for (hipEvent_t e : x->ev)
     if (e) (void)hipEventDestroy(e);
   delete x;
@@ -360,16 +549,42 @@ ems_status init_physics_tables(ems_ctx* x, const ems_material* mats, int32_t n_m
 }
 
 ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
-  if (!x || !g || !g->bounds || !g->material || !g->tally_bin)
+  if (!x || !g || (!g->bounds && g->kind != EMS_GEOM_CSG) || !g->material || !g->tally_bin)
     return fail(EMS_E_ARG, "init_geometry: null argument");
   if (!x->tables) return fail(EMS_E_STATE, "init_geometry: call init_physics_tables first");
-  if (g->kind != EMS_GEOM_SLABS && g->kind != EMS_GEOM_CYLINDERS)
+  if (g->kind != EMS_GEOM_SLABS && g->kind != EMS_GEOM_CYLINDERS && g->kind != EMS_GEOM_CSG)
     return fail(EMS_E_ARG, "init_geometry: unknown kind");
+  const bool csg = g->kind == EMS_GEOM_CSG;
+  std::vector<int> cand_off, cand;
+  if (csg) {
+    if (g->n_surf < 1 || (uint32_t)g->n_surf > kMaxSurf || !g->surfaces || !g->face_off || !g->faces)
+      return fail(EMS_E_ARG, "init_geometry: quadric cells need 1..4096 surfaces, face offsets and faces");
+    if (g->n_vol < 1 || (uint32_t)g->n_vol > kMaxVol) return fail(EMS_E_ARG, "init_geometry: 1..4096 volumes");
+    if (g->face_off[0] != 0) return fail(EMS_E_ARG, "init_geometry: face_off[0] must be 0");
+    for (int k = 0; k < g->n_vol; ++k)
+      if (g->face_off[k + 1] < g->face_off[k])
+        return fail(EMS_E_ARG, "init_geometry: face offsets must not decrease");
+    const int nf = g->face_off[g->n_vol];
+    if ((uint32_t)nf > kMaxFaces) return fail(EMS_E_ARG, "init_geometry: more than 32768 faces");
+    for (int j = 0; j < nf; ++j)
+      if (g->faces[j] < 0 || (g->faces[j] >> 1) >= g->n_surf)
+        return fail(EMS_E_ARG, "init_geometry: face names an unknown surface");
+    for (int j = 0; j < 10 * g->n_surf; ++j)
+      if (!std::isfinite(g->surfaces[j])) return fail(EMS_E_ARG, "init_geometry: surface coefficient not finite");
+    // cells entered through each face code, in increasing cell order
+    cand_off.assign(2 * (size_t)g->n_surf + 1, 0);
+    for (int j = 0; j < nf; ++j) cand_off[g->faces[j] + 1] += 1;
+    for (size_t c = 1; c < cand_off.size(); ++c) cand_off[c] += cand_off[c - 1];
+    cand.assign(nf, 0);
+    std::vector<int> fill(cand_off.begin(), cand_off.end() - 1);
+    for (int k = 0; k < g->n_vol; ++k)
+      for (int j = g->face_off[k]; j < g->face_off[k + 1]; ++j) cand[fill[g->faces[j]]++] = k;
+  }
   if (g->n_vol < 1 || (uint32_t)g->n_vol > kMaxVol) return fail(EMS_E_ARG, "init_geometry: 1..4096 volumes");
   if (g->n_bins < 1 || (uint32_t)g->n_bins > x->cfg.max_bins)
     return fail(EMS_E_ARG, "init_geometry: n_bins exceeds the configured max_bins");
   for (int i = 0; i < g->n_vol; ++i) {
-    if (!(g->bounds[i + 1] > g->bounds[i])) return fail(EMS_E_ARG, "init_geometry: bounds must increase");
+    if (!csg && !(g->bounds[i + 1] > g->bounds[i])) return fail(EMS_E_ARG, "init_geometry: bounds must increase");
     if (g->material[i] < -1 || g->material[i] >= x->P.n_mats)
       return fail(EMS_E_ARG, "init_geometry: unknown material index");
     if (g->tally_bin[i] < 0 || g->tally_bin[i] >= g->n_bins)
@@ -382,7 +597,19 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
   if (g->bz != 0.0 && !(g->field_tol > 0.0))
     return fail(EMS_E_ARG, "init_geometry: a field needs a positive field_tol");
   hipStream_t s = (hipStream_t)stream;
-  HIP_OK(hipMemcpyAsync(x->geo_bounds, g->bounds, sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
+  if (csg) {
+    const int nf = g->face_off[g->n_vol];
+    std::vector<double> zeros(g->n_vol + 1, 0.0);
+    HIP_OK(hipMemcpyAsync(x->geo_bounds, zeros.data(), sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void*)x->P.surf, g->surfaces, sizeof(double) * 10 * g->n_surf, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void*)x->P.face_off, g->face_off, sizeof(int) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void*)x->P.faces, g->faces, sizeof(int) * (nf > 0 ? nf : 0), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void*)x->P.cand_off, cand_off.data(), sizeof(int) * cand_off.size(), hipMemcpyHostToDevice, s));
+    if (nf > 0) HIP_OK(hipMemcpyAsync((void*)x->P.cand, cand.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));  // the host vectors go out of scope
+  } else {
+    HIP_OK(hipMemcpyAsync(x->geo_bounds, g->bounds, sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
+  }
   HIP_OK(hipMemcpyAsync(x->geo_mat, g->material, sizeof(int) * g->n_vol, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(x->geo_bin, g->tally_bin, sizeof(int) * g->n_vol, hipMemcpyHostToDevice, s));
   Params& P = x->P;
@@ -394,6 +621,7 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
   P.hz = g->half_z;
   P.bz = g->bz;
   P.ftol = g->field_tol;
+  P.n_surf = csg ? g->n_surf : 0;
   HIP_OK(launch_zero_u64(x->ctr, kNumLines * kLineWords, s));
   x->run_steps[0] = x->run_steps[1] = x->run_steps[2] = 0;
   HIP_OK(launch_zero_u64(P.esc_hist, 3 * kGrid, s));
@@ -408,14 +636,19 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
 namespace {
 
 // Submit a batch: slots, ring copy, slot initialisation.  Nothing changes on error.
+// The host work per event is a few array updates and one hash insert; per-event
+// sums (energy, photons) are made on the device.
 ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   const uint32_t ne = b->n_events;
   if (ne == 0) return EMS_OK;
   if (!b->event_ids || !b->offsets) return fail(EMS_E_ARG, "transport_events: null ids/offsets");
   if (b->offsets[0] != 0) return fail(EMS_E_ARG, "transport_events: offsets[0] must be 0");
-  for (uint32_t e = 0; e < ne; ++e)
-    if (b->offsets[e + 1] < b->offsets[e] + 1)
-      return fail(EMS_E_ARG, "transport_events: every event needs at least one primary");
+  const int64_t quarter = (int64_t)(x->cfg.pool_capacity / 4);
+  for (uint32_t e = 0; e < ne; ++e) {
+    const int64_t k = b->offsets[e + 1] - b->offsets[e];
+    if (k < 1) return fail(EMS_E_ARG, "transport_events: every event needs at least one primary");
+    if (k > quarter) return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
+  }
   const uint64_t n = (uint64_t)b->offsets[ne];
   if (!b->species || !b->energy || !b->pos || !b->dir)
     return fail(EMS_E_ARG, "transport_events: null primary arrays");
@@ -423,39 +656,47 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
     return fail(EMS_E_CAPACITY, "transport_events: not enough free event slots");
   if (n + x->q_count > x->cfg.queue_capacity)
     return fail(EMS_E_CAPACITY, "transport_events: primaries exceed the queue capacity");
+  const size_t nf = x->free_slots.size();
+  const uint32_t* slots = x->free_slots.data() + (nf - ne);  // taken from the back
+  // ids: insert; a repeat (unread or within the batch) undoes the inserts
+  auto undo = [&](uint32_t upto) {
+    for (uint32_t e = 0; e < upto; ++e) x->id_to_slot.erase(b->event_ids[e], x->slot_id);
+  };
   for (uint32_t e = 0; e < ne; ++e) {
-    if (x->id_to_slot.count(b->event_ids[e])) return fail(EMS_E_ARG, "transport_events: duplicate event id");
-    if ((uint64_t)(b->offsets[e + 1] - b->offsets[e]) > x->cfg.pool_capacity / 4)
-      return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
+    const uint32_t sl = slots[e];
+    x->slot_id[sl] = b->event_ids[e];
+    if (!x->id_to_slot.insert(b->event_ids[e], sl, x->slot_id)) {
+      undo(e);
+      return fail(EMS_E_ARG, "transport_events: duplicate event id");
+    }
   }
-  {
-    std::vector<uint32_t> ids(b->event_ids, b->event_ids + ne);
-    if (!std::is_sorted(ids.begin(), ids.end())) std::sort(ids.begin(), ids.end());
-    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
-      return fail(EMS_E_ARG, "transport_events: duplicate event id in batch");
-  }
-  std::vector<uint32_t> slots(ne);
-  for (uint32_t e = 0; e < ne; ++e) slots[e] = x->free_slots[x->free_slots.size() - 1 - e];
-  HIP_OK(hipMemcpyAsync(x->stage_off, b->offsets, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(x->stage_slot, slots.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s));
   const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
   // validity flags of the batch's primaries: a word of the done line, unused otherwise
   unsigned long long* bad = x->ctr + kLDone * kLineWords + 1;
-  HIP_OK(launch_zero_u64(bad, 1, s));
-  HIP_OK(launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species,
-                        b->energy, b->pos, b->dir, (uint32_t)n, bad, s));
-  HIP_OK(launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, x->e_in,
-                           x->scale, x->stage_out, s));
-  // primary energy per event (admission energy budget) and photons per event (pool sizes)
   std::vector<double> ev_e(ne);
-  std::vector<int32_t> sp(n);
-  HIP_OK(hipMemcpyAsync(ev_e.data(), x->stage_out, ne * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(sp.data(), b->species, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> ev_g(ne);
   unsigned long long badw = 0;
-  HIP_OK(hipMemcpyAsync(&badw, bad, sizeof(badw), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  hipError_t e = hipMemcpyAsync(x->stage_off, b->offsets, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(x->stage_slot, slots, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_zero_u64(bad, 1, s);
+  if (e == hipSuccess)
+    e = launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species, b->energy,
+                       b->pos, b->dir, (uint32_t)n, bad, s);
+  if (e == hipSuccess)
+    e = launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, x->e_in,
+                          x->scale, x->stage_out, x->stage_ng, s);
+  // primary energy (admission energy budget) and photons (pool sizes) per event
+  if (e == hipSuccess) e = hipMemcpyAsync(ev_e.data(), x->stage_out, ne * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ev_g.data(), x->stage_ng, ne * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&badw, bad, sizeof(badw), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    undo(ne);
+    return fail(EMS_E_HIP, std::string("transport_events: ") + hipGetErrorString(e));
+  }
   if (badw) {
+    undo(ne);
     std::string m = "transport_events: invalid primaries:";
     if (badw & 1ull) m += " species not 0, 1 or 2;";
     if (badw & 2ull) m += " kinetic energy not in (0, 1e5] MeV;";
@@ -463,20 +704,13 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
     if (badw & 8ull) m += " direction not a unit vector;";
     return fail(EMS_E_ARG, m);
   }
-  for (uint64_t r = 0; r < n; ++r)
-    if (sp[r] < 0 || sp[r] > 2) return fail(EMS_E_ARG, "transport_events: species must be 0, 1 or 2");
-  x->id_to_slot.reserve(x->id_to_slot.size() + ne);
-  for (uint32_t e = 0; e < ne; ++e) {
-    const uint32_t sl = slots[e];
-    x->free_slots.pop_back();
+  for (uint32_t j = 0; j < ne; ++j) {
+    const uint32_t sl = slots[j];
     x->slot_state[sl] = 1;
-    x->slot_id[sl] = b->event_ids[e];
-    x->slot_e[sl] = ev_e[e];
-    x->id_to_slot[b->event_ids[e]] = sl;
-    uint32_t ng = 0;
-    for (int64_t r = b->offsets[e]; r < b->offsets[e + 1]; ++r) ng += sp[r] == EMS_GAMMA;
-    x->pending.push_back({sl, (uint32_t)(b->offsets[e + 1] - b->offsets[e]), ng, ev_e[e]});
+    x->slot_e[sl] = ev_e[j];
+    x->pending.push_back({sl, (uint32_t)(b->offsets[j + 1] - b->offsets[j]), ev_g[j], ev_e[j]});
   }
+  x->free_slots.resize(nf - ne);
   x->q_count += (uint32_t)n;
   x->pending_prims += n;
   return EMS_OK;
@@ -518,7 +752,8 @@ ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
 // so every launch covers at most `bound` tracks: twice the pool at the start of
 // the interval plus a margin, or the whole capacity when full_room is set.
 struct IntervalOut {
-  uint64_t stepped = 0, deferred = 0, busy = 0, peak = 0;
+  uint64_t stepped = 0, deferred = 0, busy = 0, peak = 0, spilled = 0;
+  bool stalled = false;
 };
 
 constexpr uint32_t kBoundMargin = 65536;
@@ -530,11 +765,71 @@ constexpr uint32_t kStepsPerLaunch = 4;
 constexpr uint64_t kTailTracks = 16384;
 constexpr uint32_t kTailStepsPerLaunch = 32;
 constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
+constexpr size_t kLogCap = size_t(1) << 20;  // iteration records kept
+
+// Bring back tracks waiting in host memory once the pool has drained below a quarter
+// of its capacity, up to half of it, last spilled first.  Runs where admission
+// would: no new event is admitted while tracks wait (older work first).
+ems_status unspill(ems_ctx* x, hipStream_t s) {
+  const uint64_t cap = x->cfg.pool_capacity, n = (uint64_t)x->nG + x->nC;
+  if (x->spill_top == 0 || n >= cap / 4) return EMS_OK;
+  const uint64_t m = std::min<uint64_t>(x->spill_top, cap / 2 - n);
+  const uint64_t a = x->spill_top - m;
+  uint32_t mg = 0;
+  for (uint64_t r = a; r < x->spill_top; ++r) mg += (x->hs.meta[r] & 3u) == EMS_GAMMA;
+  // staging: the bottom of the free photon buffer
+  HIP_OK(copy_rows(x->pool[0][1 - x->cur], 0, x->hs, a, m, hipMemcpyHostToDevice, s));
+  HIP_OK(launch_unspill(x->P, x->set, x->cfg.pool_capacity, x->cur, (uint32_t)m, s));
+  x->spill_top = a;
+  x->nG += mg;
+  x->nC += (uint32_t)m - mg;
+  return EMS_OK;
+}
+
+// Move the tracks of the highest energies to host memory: the fewest top bins of the
+// energy grid that hold at least `want` tracks, fewer if the host room is smaller.
+ems_status spill(ems_ctx* x, hipStream_t s, uint64_t want, uint64_t* moved) {
+  *moved = 0;
+  const uint64_t room = x->cfg.spill_capacity - x->spill_top;
+  const uint32_t N = x->cfg.pool_capacity;
+  if (want == 0 || room == 0 || x->nG + x->nC == 0) return EMS_OK;
+  std::vector<uint64_t> h(kGrid);
+  HIP_OK(launch_zero_u64(x->spill_hist, kGrid, s));
+  HIP_OK(launch_spill_hist(x->P, x->set, N, x->cur, x->nG, x->nC, x->spill_hist, s));
+  HIP_OK(hipMemcpyAsync(h.data(), x->spill_hist, kGrid * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int b = kGrid;
+  uint64_t c = 0;
+  while (b > 0 && c < want) c += h[--b];
+  while (b < kGrid && c > room) c -= h[b++];
+  if (c == 0) return EMS_OK;
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  HIP_OK(launch_zero_u32(x->spill_cnt, 4, s));
+  HIP_OK(launch_spill_split(x->P, x->set, N, x->cur, x->nG, x->nC, b, x->spill_cnt, s));
+  HIP_OK(hipMemcpyAsync(cnt, x->spill_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if ((uint64_t)cnt[2] + cnt[3] != c || (uint64_t)cnt[0] + cnt[1] + c != (uint64_t)x->nG + x->nC)
+    return fail(EMS_E_INTERNAL, "transport_events: spill counts disagree");
+  const int o = 1 - x->cur;
+  HIP_OK(copy_rows(x->pool[0][o], N - cnt[2], x->hs, x->spill_top, cnt[2], hipMemcpyDeviceToHost, s));
+  HIP_OK(copy_rows(x->pool[1][o], N - cnt[3], x->hs, x->spill_top + cnt[2], cnt[3],
+                   hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  x->spill_top += c;
+  x->cur = o;
+  x->nG = cnt[0];
+  x->nC = cnt[1];
+  *moved = c;
+  return EMS_OK;
+}
 
 ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
                         bool admit_first, bool full_room, IntervalOut* io) {
-  HIP_OK(launch_iter_begin(x->ctr, true, x->nG, x->nC, s));
-  if (admit_first) {
+  HIP_OK(launch_iter_begin(x->ctr, true, x->nG, x->nC, 0, nullptr, s));
+  if (admit_first && x->spill_top > 0) {
+    const ems_status st = unspill(x, s);
+    if (st != EMS_OK) return st;
+  } else if (admit_first) {
     uint32_t m = 0;
     const ems_status st = admit(x, s, &m);
     if (st != EMS_OK) return st;
@@ -551,7 +846,7 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
       full_room ? cap : (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(n0, 2 * n0 + kBoundMargin));
   const uint32_t msteps = full_room ? 1u : (n0 < kTailTracks ? kTailStepsPerLaunch : kStepsPerLaunch);
   for (int j = 0; j < iters; ++j) {
-    if (j > 0) HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, s));
+    if (j > 0) HIP_OK(launch_iter_begin(x->ctr, false, 0, 0, (uint32_t)j, x->iter_log, s));
     if (x->ev[2 * j]) HIP_OK(hipEventRecord(x->ev[2 * j], s));
     HIP_OK(launch_iteration(x->P, x->set, cap, x->cur, x->iq, bound, msteps, mixed, rec, s));
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
@@ -561,6 +856,9 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, pre * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  uint32_t ilog[4 * kMaxPerSync];
+  if (iters > 1)
+    HIP_OK(hipMemcpyAsync(ilog, x->iter_log, 4 * (iters - 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const unsigned long long* L = x->h_ctr;
   unsigned long long S[kLineWords] = {};
@@ -582,11 +880,33 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   x->stats.tracks_in += S[kSIn];
   x->stats.tracks_out += S[kSOut] + outG + outC;
   x->stats.queued += S[kSQueued] + queued_last;
+  float it_ms[kMaxPerSync] = {};
   if (x->ev[0]) {
     for (int j = 0; j < iters; ++j) {
-      float ms = 0.f;
-      HIP_OK(hipEventElapsedTime(&ms, x->ev[2 * j], x->ev[2 * j + 1]));
-      x->stats.kernel_ms += ms;
+      HIP_OK(hipEventElapsedTime(&it_ms[j], x->ev[2 * j], x->ev[2 * j + 1]));
+      x->stats.kernel_ms += it_ms[j];
+    }
+  }
+  {  // per-iteration records: the device logged all but the last, read from the counters
+    const unsigned long long in_last = L[kLAdmit * kLineWords];
+    for (int j = 0; j < iters && x->log.size() < kLogCap; ++j) {
+      ems_iteration_record r{};
+      if (j + 1 < iters) {
+        r.photons = ilog[4 * j];
+        r.charged = ilog[4 * j + 1];
+        r.interactions = ilog[4 * j + 2];
+        r.tracks_out = ilog[4 * j + 3];
+      } else {
+        r.photons = (uint32_t)(in_last & 0xFFFFFFFFull);
+        r.charged = (uint32_t)(in_last >> 32);
+        r.interactions = (uint32_t)queued_last;
+        r.tracks_out = outG + outC;
+      }
+      if (r.photons + r.charged == 0) continue;
+      r.waiting_primaries = x->pending_prims;
+      r.spilled = x->spill_top;
+      r.ms = it_ms[j];
+      x->log.push_back(r);
     }
   }
   if (n_done) {
@@ -609,7 +929,7 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   io->deferred += S[kSDeferred];
   io->busy += S[kSBusy];
   io->peak = std::max<uint64_t>(io->peak, S[kSPeak]);
-  if (S[kSStall]) return fail(EMS_E_CAPACITY, "transport_events: pool full, no track can step");
+  io->stalled = io->stalled || S[kSStall] != 0;
   return EMS_OK;
 }
 
@@ -630,13 +950,26 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
   IntervalOut io;
   io.peak = (uint64_t)x->nG + x->nC;
   const int per_sync = x->per_sync;
+  const uint64_t cap = x->cfg.pool_capacity;
   while (max_iterations < 0 || it < (uint64_t)max_iterations) {
-    if (x->nG + x->nC == 0 && x->pending.empty()) break;
+    if (x->nG + x->nC == 0 && x->pending.empty() && x->spill_top == 0) break;
     int k = per_sync;
     if (max_iterations >= 0) k = (int)std::min<uint64_t>((uint64_t)k, (uint64_t)max_iterations - it);
-    const ems_status st = run_interval(x, s, nullptr, k, true, false, &io);
+    ems_status st = run_interval(x, s, nullptr, k, true, false, &io);
     if (st != EMS_OK) return st;
     it += k;
+    // a pool above three quarters of its capacity, or one that cannot progress,
+    // sends its highest-energy tracks to host memory down to half its capacity
+    const uint64_t n = (uint64_t)x->nG + x->nC;
+    if (x->cfg.spill_capacity > 0 && (io.stalled || n > cap - cap / 4)) {
+      uint64_t moved = 0;
+      st = spill(x, s, std::max<uint64_t>(n > cap / 2 ? n - cap / 2 : 0, io.stalled ? n / 2 : 0), &moved);
+      if (st != EMS_OK) return st;
+      io.spilled += moved;
+      if (moved) io.stalled = false;
+    }
+    if (io.stalled)
+      return fail(EMS_E_STALLED, "transport_events: pool full of put-off interactions, no track can step");
   }
   const uint64_t stepped = io.stepped, deferred = io.deferred, peak = io.peak;
   if (progress) {
@@ -647,51 +980,84 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
     progress->track_steps = stepped;
     progress->deferred = deferred;
     progress->peak_alive = peak;
+    progress->spilled = x->spill_top;
+    progress->spilled_total = io.spilled;
   }
   return EMS_OK;
 }
 
 ems_status tally_read(ems_ctx* x, uint32_t n, const uint32_t* ids, double* dep, double* ledger,
-                      int32_t* status, void* stream) {
+                      uint64_t* steps, uint64_t* esc_hist, int32_t* status, void* stream) {
   if (!x || (n && (!ids || !dep || !ledger || !status))) return fail(EMS_E_ARG, "tally_read: null argument");
   if (!x->geometry) return fail(EMS_E_STATE, "tally_read: no geometry");
+  if (esc_hist && !x->P.ev_esc)
+    return fail(EMS_E_STATE, "tally_read: per-event escape spectra need EMS_FLAG_EVENT_ESCAPE");
   hipStream_t s = (hipStream_t)stream;
   std::vector<uint32_t> slots;
   std::vector<uint32_t> rows;
   bool all = true;
   for (uint32_t j = 0; j < n; ++j) {
-    auto it = x->id_to_slot.find(ids[j]);
-    if (it == x->id_to_slot.end()) {
+    const int64_t f = x->id_to_slot.find(ids[j], x->slot_id);
+    const uint32_t sl = (uint32_t)f;
+    if (f < 0) {
       status[j] = EMS_E_ARG;
       all = false;
-    } else if (x->slot_state[it->second] != 2) {
+    } else if (x->slot_state[sl] == 3) {  // already read earlier in this call
+      status[j] = EMS_E_ARG;
+      all = false;
+    } else if (x->slot_state[sl] != 2) {
       status[j] = EMS_NOT_READY;
       all = false;
     } else {
       status[j] = EMS_OK;
-      slots.push_back(it->second);
+      x->slot_state[sl] = 3;
+      slots.push_back(sl);
       rows.push_back(j);
     }
   }
   const uint32_t nb = (uint32_t)x->P.nbins;
-  const uint32_t w = nb + 5;
+  const uint32_t w = nb + kRowLedger;
   const uint32_t chunk = x->cfg.max_events;
+  const uint32_t ne = 3 * kGrid;
   std::vector<double> buf;
-  for (size_t a = 0; a < slots.size(); a += chunk) {
+  ems_status st = EMS_OK;
+  for (size_t a = 0; a < slots.size() && st == EMS_OK; a += chunk) {
     const uint32_t m = (uint32_t)std::min<size_t>(chunk, slots.size() - a);
-    HIP_OK(hipMemcpyAsync(x->stage_slot, slots.data() + a, m * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_OK(launch_gather_tallies(x->P, x->stage_slot, m, x->e_in, x->stage_out, s));
+    hipError_t e = hipMemcpyAsync(x->stage_slot, slots.data() + a, m * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_gather_tallies(x->P, x->stage_slot, m, x->e_in, x->stage_out,
+                                esc_hist ? x->stage_esc : nullptr, s);
     buf.resize((size_t)m * w);
-    HIP_OK(hipMemcpyAsync(buf.data(), x->stage_out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(buf.data(), x->stage_out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && esc_hist) {
+      std::vector<uint64_t> eb((size_t)m * ne);
+      e = hipMemcpyAsync(eb.data(), x->stage_esc, eb.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      for (uint32_t r = 0; e == hipSuccess && r < m; ++r)
+        std::memcpy(esc_hist + (size_t)rows[a + r] * ne, eb.data() + (size_t)r * ne, ne * sizeof(uint64_t));
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = fail(EMS_E_HIP, std::string("tally_read: ") + hipGetErrorString(e));
+      break;
+    }
     for (uint32_t r = 0; r < m; ++r) {
       const uint32_t j = rows[a + r];
-      std::memcpy(dep + (size_t)j * nb, buf.data() + (size_t)r * w, nb * sizeof(double));
-      std::memcpy(ledger + (size_t)j * 5, buf.data() + (size_t)r * w + nb, 5 * sizeof(double));
+      const double* row = buf.data() + (size_t)r * w;
+      std::memcpy(dep + (size_t)j * nb, row, nb * sizeof(double));
+      std::memcpy(ledger + (size_t)j * 5, row + nb, 5 * sizeof(double));
+      if (steps)
+        for (int k = 0; k < 3; ++k) steps[(size_t)j * 3 + k] = (uint64_t)row[nb + 5 + k];
     }
   }
-  for (uint32_t sl : slots) {  // release
-    x->id_to_slot.erase(x->slot_id[sl]);
+  if (st != EMS_OK) {  // nothing is released: every event stays readable
+    for (uint32_t sl : slots) x->slot_state[sl] = 2;
+    return st;
+  }
+  for (uint32_t sl : slots) {  // release, once per slot
+    x->id_to_slot.erase(x->slot_id[sl], x->slot_id);
     x->slot_state[sl] = 0;
     x->free_slots.push_back(sl);
   }
@@ -707,6 +1073,16 @@ ems_status ems_run_counters(ems_ctx* x, uint64_t* steps, uint64_t* esc_hist, voi
     HIP_OK(hipStreamSynchronize(s));
   }
   for (int i = 0; i < 3; ++i) steps[i] = x->run_steps[i];
+  return EMS_OK;
+}
+
+ems_status ems_iteration_log(ems_ctx* x, ems_iteration_record* out, uint64_t max, uint64_t* n,
+                             int32_t reset) {
+  if (!x || !n || (max > 0 && !out)) return fail(EMS_E_ARG, "ems_iteration_log: null argument");
+  *n = x->log.size();
+  const uint64_t m = std::min<uint64_t>(max, x->log.size());
+  if (m) std::memcpy(out, x->log.data(), m * sizeof(ems_iteration_record));
+  if (reset) x->log.clear();
   return EMS_OK;
 }
 
@@ -727,7 +1103,7 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   // every slot of this context is reset: step_once discards any events in flight
   reset_events(x);
   HIP_OK(launch_slots_reset(x->P, s));
-  HIP_OK(launch_iter_begin(x->ctr, true, 0, 0, s));
+  HIP_OK(launch_iter_begin(x->ctr, true, 0, 0, 0, nullptr, s));
   HIP_OK(launch_pool_load(x->P, x->set, x->cfg.pool_capacity, *in, n, s));
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));

@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "emshower.h"
 #include "ems_device.h"
 
@@ -221,8 +223,130 @@ __device__ __forceinline__ R range_inverse(const Params& P, const R* tb, R r, in
 
 // ------------------------------------------------------------------ geometry
 
+
+// Quadric-surface cells (paper Sec. 2.3 "Geometry and EM fields": the ORANGE model,
+// cells bounded by quadric surfaces and told apart by their sense to each surface,
+// one level).  Surface f(x) = qxx x^2 + qyy y^2 + qzz z^2 + qxy xy + qyz yz + qzx zx
+// + px x + py y + pz z + k; a cell is the intersection of half-spaces f < 0 (side -1)
+// or f > 0 (side +1).  Along a ray, f = a t^2 + B t + c.  Every expression is
+// evaluated unfused in the order written: sides are decided by the sign of values
+// that vanish on the surfaces.
+__device__ __forceinline__ double csg_c(const double* q, double x, double y, double z) {
+#pragma clang fp contract(off)
+  return q[0] * x * x + q[1] * y * y + q[2] * z * z + q[3] * x * y + q[4] * y * z + q[5] * z * x +
+         q[6] * x + q[7] * y + q[8] * z + q[9];
+}
+__device__ __forceinline__ double csg_B(const double* q, double x, double y, double z, double u,
+                                        double v, double w) {
+#pragma clang fp contract(off)
+  return 2.0 * (q[0] * x * u + q[1] * y * v + q[2] * z * w) + q[3] * (x * v + y * u) +
+         q[4] * (y * w + z * v) + q[5] * (z * u + x * w) + q[6] * u + q[7] * v + q[8] * w;
+}
+__device__ __forceinline__ double csg_a(const double* q, double u, double v, double w) {
+#pragma clang fp contract(off)
+  return q[0] * u * u + q[1] * v * v + q[2] * w * w + q[3] * u * v + q[4] * v * w + q[5] * w * u;
+}
+
+// Side of surface q at (x,y,z) moving along (u,v,w): sign of f, on the surface the
+// sign of df/dt, on a tangent the sign of a (zero counts as +1).
+__device__ __forceinline__ int csg_side(const double* q, double x, double y, double z, double u,
+                                        double v, double w) {
+  const double c = csg_c(q, x, y, z);
+  if (c > 0.0) return 1;
+  if (c < 0.0) return -1;
+  const double B = csg_B(q, x, y, z, u, v, w);
+  if (B > 0.0) return 1;
+  if (B < 0.0) return -1;
+  return csg_a(q, u, v, w) >= 0.0 ? 1 : -1;
+}
+
+// Distance to where f leaves side sg: the root at which df/dt has the sign -sg,
+// written without cancellation; a root behind counts as 0 if the track is moving
+// off side sg right now, else as no crossing.
+__device__ __forceinline__ double csg_exit(const double* q, double x, double y, double z, double u,
+                                           double v, double w, double sg) {
+#pragma clang fp contract(off)
+  const double a = csg_a(q, u, v, w);
+  const double B = csg_B(q, x, y, z, u, v, w);
+  const double c = csg_c(q, x, y, z);
+  const double b = 0.5 * B;
+  double t;
+  if (a == 0.0) {
+    if (!(sg * b < 0.0)) return HUGE_VAL;
+    t = c / (-2.0 * b);
+  } else {
+    const double D = b * b - a * c;
+    if (!(D > 0.0)) return HUGE_VAL;
+    const double r = sqrt(D);
+    t = sg * b <= 0.0 ? c / (-b + sg * r) : (-b - sg * r) / a;
+  }
+  if (!(t >= 0.0)) return sg * b < 0.0 ? 0.0 : HUGE_VAL;
+  return t;
+}
+
+// Does cell m hold the point moving along (u,v,w)?  Faces on surface `forced` count
+// as satisfied.
+__device__ __forceinline__ bool csg_holds(const Params& P, int m, double x, double y, double z,
+                                          double u, double v, double w, int forced) {
+  for (int j = P.face_off[m]; j < P.face_off[m + 1]; ++j) {
+    const int f = P.faces[j];
+    if ((f >> 1) == forced) continue;
+    if (csg_side(P.surf + 10 * (f >> 1), x, y, z, u, v, w) != ((f & 1) ? 1 : -1)) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ int csg_locate(const Params& P, double x, double y, double z, double u,
+                                          double v, double w) {
+  for (int m = 0; m < P.nvol; ++m)
+    if (csg_holds(P, m, x, y, z, u, v, w, -1)) return m;
+  return -1;
+}
+
+// Boundary distance in cell k and the cell entered: the nearest exit over the cell's
+// faces (first face wins ties); entered = the first cell with the crossed surface on
+// the other side whose remaining faces hold at the crossing point, else the first
+// other cell without the crossed surface on the side left that holds it, else none.
+__device__ __forceinline__ double csg_distance(const Params& P, int k, double px, double py,
+                                               double pz, double dx, double dy, double dz,
+                                               int& next) {
+#pragma clang fp contract(off)
+  double s_min = HUGE_VAL;
+  int left = -1;
+  for (int j = P.face_off[k]; j < P.face_off[k + 1]; ++j) {
+    const int f = P.faces[j];
+    const double t = csg_exit(P.surf + 10 * (f >> 1), px, py, pz, dx, dy, dz, (f & 1) ? 1.0 : -1.0);
+    if (t < s_min) {
+      s_min = t;
+      left = f;
+    }
+  }
+  next = -1;
+  if (left < 0) return HUGE_VAL;
+  const int s = left >> 1, entered = left ^ 1;
+  const double x = px + s_min * dx, y = py + s_min * dy, z = pz + s_min * dz;
+  for (int j = P.cand_off[entered]; j < P.cand_off[entered + 1]; ++j) {
+    const int m = P.cand[j];
+    if (m != k && csg_holds(P, m, x, y, z, dx, dy, dz, s)) {
+      next = m;
+      return s_min;
+    }
+  }
+  for (int m = 0; m < P.nvol; ++m) {
+    if (m == k) continue;
+    bool has_left = false;
+    for (int j = P.face_off[m]; j < P.face_off[m + 1]; ++j) has_left |= P.faces[j] == left;
+    if (!has_left && csg_holds(P, m, x, y, z, dx, dy, dz, s)) {
+      next = m;
+      return s_min;
+    }
+  }
+  return s_min;
+}
+
 __device__ __forceinline__ int locate(const Params& P, double x, double y, double z, double u,
                                       double v, double w) {
+  if (P.gkind == EMS_GEOM_CSG) return csg_locate(P, x, y, z, u, v, w);
   if (P.gkind == EMS_GEOM_SLABS) {
     if (fabs(x) > P.hx || fabs(y) > P.hy) return -1;
     for (int j = 0; j < P.nvol; ++j) {
@@ -248,6 +372,7 @@ __device__ __forceinline__ double distance(const Params& P, const double* bounds
                                            double px, double py, double pz, double dx, double dy,
                                            double dz, int& next) {
 #pragma clang fp contract(off)
+  if (P.gkind == EMS_GEOM_CSG) return csg_distance(P, vol, px, py, pz, dx, dy, dz, next);
   double s = HUGE_VAL;
   int nx = -1;
   if (P.gkind == EMS_GEOM_SLABS) {
@@ -932,30 +1057,36 @@ __device__ __forceinline__ unsigned long long fixed_point(double e, double scale
   return (unsigned long long)llrint(e * scale);
 }
 
-// Per-event scores of one block -- tally bins, ledger words, escape-spectrum bins
-// and changes of the events' alive counts -- are summed in an LDS hash table and
-// added to global memory once per distinct key.  The sums are integers (fixed-point
-// energies, counts), so grouping them changes no result.  Key = tag << 29 | index.
+// Per-event scores of one block -- tally bins, ledger words, escape-spectrum bins,
+// track-steps by species and changes of the events' alive counts -- are summed in
+// an LDS hash table and added to global memory once per distinct key.  The sums are
+// integers (fixed-point energies, counts), so grouping them changes no result.
+// Key = tag << 28 | index.
 constexpr int kAggSlots = 512;
 constexpr int kAggProbes = 32;
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kAggIndexBits = 28;
 enum AggTag : uint32_t {
   kTagTally = 0,   // index = slot * nbins + bin
   kTagLedger = 1,  // tags 1..4: ledger word tag - 1, index = slot
   kTagAlive = 5,   // index = slot, value = change of the alive count (two's complement)
-  kTagEsc = 6      // index = species * kGrid + bin of the escape spectrum
+  kTagEsc = 6,     // index = species * kGrid + bin of the run's escape spectrum
+  kTagSteps = 7,   // index = slot * 3 + species: track-steps of the event
+  kTagEvEsc = 8    // index = (slot * 3 + species) * kGrid + bin: the event's escape spectrum
 };
 struct Agg {
   uint32_t key[kAggSlots];
   unsigned long long val[kAggSlots];
 };
 
-__device__ __forceinline__ uint32_t agg_key(uint32_t tag, uint32_t index) { return (tag << 29) | index; }
+__device__ __forceinline__ uint32_t agg_key(uint32_t tag, uint32_t index) {
+  return (tag << kAggIndexBits) | index;
+}
 
 // Add one aggregated score to global memory.  An alive count that reaches zero
 // puts its event slot on the finished list.
 __device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsigned long long v) {
-  const uint32_t tag = key >> 29, idx = key & 0x1FFFFFFFu;
+  const uint32_t tag = key >> kAggIndexBits, idx = key & ((1u << kAggIndexBits) - 1u);
   if (tag == kTagTally) {
     atomicAdd(&P.tally[idx], v);
   } else if (tag < kTagAlive) {
@@ -967,8 +1098,12 @@ __device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsign
       const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
       if (k < P.max_events) P.done[k] = idx;
     }
-  } else {
+  } else if (tag == kTagEsc) {
     atomicAdd(&P.esc_hist[idx], v);
+  } else if (tag == kTagSteps) {
+    atomicAdd(&P.ledger[(size_t)(idx / 3u) * kLedger + kLedgerSteps + idx % 3u], v);
+  } else {
+    atomicAdd(&P.ev_esc[idx], v);
   }
 }
 
@@ -1163,7 +1298,10 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       const double tt = (log(o.esc) - P.lnE0) * P.inv_dlnE;
       const int b = !(tt > 0.0) ? 0 : (tt >= (double)(kGrid - 1) ? kGrid - 1 : (int)tt);
       agg_add(P, sh_agg, agg_key(kTagEsc, (uint32_t)(t.sp * kGrid + b)), 1ull);
+      if (P.ev_esc)
+        agg_add(P, sh_agg, agg_key(kTagEvEsc, (e * 3u + (uint32_t)t.sp) * kGrid + (uint32_t)b), 1ull);
     }
+    if (nsteps) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), nsteps);
     if (o.dest == -2) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
     if (rec && stepped) {
       ems_step_record& r = rec[t.src];
@@ -1479,9 +1617,11 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, IQueue Q, Pool S,
 // counter line and set the admission cursors to (nG, nC).  Otherwise continue from
 // the previous iteration: its output counts (transport survivors plus tracks
 // written by the interaction kernel) become this iteration's pool sizes, its output
-// and queue sizes are added to the interval statistics and cleared.
+// and queue sizes are added to the interval statistics and cleared, and its record
+// -- pool sizes in, interactions queued, pool size out -- goes to log[j - 1] for
+// iteration j of the interval.
 __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint32_t nG,
-                             uint32_t nC) {
+                             uint32_t nC, uint32_t j_iter, uint32_t* log) {
   const int j = threadIdx.x;
   if (explicit_counts) {
     if (j < kNumLines * kLineWords)
@@ -1495,6 +1635,14 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
     const unsigned long long v = ctr[(kLQueue + l) * kLineWords];
     queued += (v & 0xFFFFFFFFull) + (v >> 32);
     ctr[(kLQueue + l) * kLineWords] = 0ull;
+  }
+  if (log && j_iter > 0) {
+    const unsigned long long in = ctr[kLAdmit * kLineWords];
+    uint32_t* r = log + (size_t)(j_iter - 1) * 4;
+    r[0] = (uint32_t)(in & 0xFFFFFFFFull);
+    r[1] = (uint32_t)(in >> 32);
+    r[2] = (uint32_t)queued;
+    r[3] = (uint32_t)((out & 0xFFFFFFFFull) + (out >> 32));
   }
   ctr[kLStats * kLineWords + kSOut] += (out & 0xFFFFFFFFull) + (out >> 32);
   ctr[kLStats * kLineWords + kSQueued] += queued;
@@ -1579,29 +1727,36 @@ __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint
 // Tallies and ledger zeroed.
 __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots,
                              const double* T, const int32_t* sp, double* e_in, double* scale,
-                             double* e_row) {
+                             double* e_row, uint32_t* g_row) {
   const uint32_t e = blockIdx.x;
   const int64_t a = off[e], b = off[e + 1];
   __shared__ double part[kBlock];
   __shared__ double partm[kBlock];
+  __shared__ uint32_t partg[kBlock];
   double s = 0.0, sm = 0.0;
+  uint32_t ng = 0;
   for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) {
     s += T[r];
     sm += T[r] + (sp[r] == EMS_POSITRON ? 2.0 * kMe : 0.0);
+    ng += sp[r] == EMS_GAMMA ? 1u : 0u;
   }
   part[threadIdx.x] = s;
   partm[threadIdx.x] = sm;
+  partg[threadIdx.x] = ng;
   __syncthreads();
   for (int h = kBlock / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
       part[threadIdx.x] += part[threadIdx.x + h];
       partm[threadIdx.x] += partm[threadIdx.x + h];
+      partg[threadIdx.x] += partg[threadIdx.x + h];
     }
     __syncthreads();
   }
   const uint32_t slot = slots[e];
   for (int j = threadIdx.x; j < P.nbins; j += blockDim.x) P.tally[(size_t)slot * P.nbins + j] = 0ull;
   if (threadIdx.x < kLedger) P.ledger[(size_t)slot * kLedger + threadIdx.x] = 0ull;
+  if (P.ev_esc)
+    for (int j = threadIdx.x; j < 3 * kGrid; j += blockDim.x) P.ev_esc[(size_t)slot * 3 * kGrid + j] = 0ull;
   if (threadIdx.x == 0) {
     const double E = part[0], Emax = partm[0];
     int ex = 0;
@@ -1610,9 +1765,108 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
     }
     e_in[slot] = E;
     e_row[e] = E;  // per batch row, read back by the host
+    g_row[e] = partg[0];
     scale[slot] = ldexp(1.0, 61 - ex);
     P.alive[slot] = (int)(b - a);
   }
+}
+
+// ------------------------------------------------------------------ spilling to host memory
+//
+// When the pool runs full, the tracks of highest kinetic energy -- those that would
+// still multiply -- are moved out to host memory and brought back once the pool has
+// drained (paper Sec. 3.2: preferring lower-energy particles lowers the capacity a
+// shower needs; secondaries may wait in CPU memory).  A track's random numbers are
+// keyed by its lineage and step count, so where and when it waits changes no result.
+
+__device__ __forceinline__ int energy_bin(const Params& P, double T) {
+  const double t = (log(T) - P.lnE0) * P.inv_dlnE;
+  return !(t > 0.0) ? 0 : (t >= (double)(kGrid - 1) ? kGrid - 1 : (int)t);
+}
+
+__device__ __forceinline__ void copy_track(const Pool& p, size_t from, size_t to) {
+  p.x[to] = p.x[from];
+  p.y[to] = p.y[from];
+  p.z[to] = p.z[from];
+  p.u[to] = p.u[from];
+  p.v[to] = p.v[from];
+  p.w[to] = p.w[from];
+  p.T[to] = p.T[from];
+  p.nlam[to] = p.nlam[from];
+  p.k0[to] = p.k0[from];
+  p.k1[to] = p.k1[from];
+  p.k2[to] = p.k2[from];
+  p.evt[to] = p.evt[from];
+  p.nstep[to] = p.nstep[from];
+  p.meta[to] = p.meta[from];
+}
+
+// Histogram of the tracks of both class pools (buffer cur) over the energy grid.
+__global__ void k_spill_hist(Params P, Pool S, uint32_t N, int cur, uint32_t nG, uint32_t nC,
+                             unsigned long long* hist) {
+  __shared__ uint32_t h[kGrid];
+  for (int j = threadIdx.x; j < kGrid; j += blockDim.x) h[j] = 0u;
+  __syncthreads();
+  const uint32_t n = nG + nC;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const bool c = i >= nG;
+    const double T = S.T[buf_off(c, cur, N) + (c ? i - nG : i)];
+    atomicAdd(&h[energy_bin(P, T)], 1u);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kGrid; j += blockDim.x)
+    if (h[j]) atomicAdd(&hist[j], (unsigned long long)h[j]);
+}
+
+// Split each class pool of buffer cur into buffer 1 - cur: tracks in energy bins >=
+// bmin to its top (index N-1 downward), the others compacted at its bottom.
+// cnt = kept photons, kept charged, spilled photons, spilled charged.  Blocks
+// [0, nbG) take photons, the rest charged tracks, so a wavefront holds one class.
+__global__ void k_spill_split(Params P, Pool S, uint32_t N, int cur, uint32_t nG, uint32_t nC,
+                              int bmin, uint32_t* cnt) {
+  const uint32_t nbG = (nG + blockDim.x - 1) / blockDim.x;
+  const bool c = blockIdx.x >= nbG;
+  const uint32_t n = c ? nC : nG;
+  const uint32_t i = (blockIdx.x - (c ? nbG : 0u)) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n;
+  const size_t from = buf_off(c, cur, N) + i;
+  bool out = false;
+  if (valid) out = energy_bin(P, S.T[from]) >= bmin;
+  const uint64_t mk = __ballot(valid && !out), ms = __ballot(out);
+  uint32_t bk = 0, bs = 0;
+  if (lane == 0) {
+    if (mk) bk = atomicAdd(&cnt[c ? 1 : 0], (uint32_t)__popcll(mk));
+    if (ms) bs = atomicAdd(&cnt[c ? 3 : 2], (uint32_t)__popcll(ms));
+  }
+  bk = __shfl(bk, 0);
+  bs = __shfl(bs, 0);
+  if (!valid) return;
+  const size_t o = buf_off(c, 1 - cur, N);
+  const size_t to = out ? o + (N - 1u - (bs + lanes_below(ms, lane))) : o + bk + lanes_below(mk, lane);
+  copy_track(S, from, to);
+}
+
+// Bring m tracks back from host memory: they were copied to the bottom of the photon
+// buffer 1 - cur and are appended here to the pool of their class (buffer cur) at
+// the admission cursors, one atomic per wavefront and class.
+__global__ void k_unspill(Params P, Pool S, uint32_t N, int cur, uint32_t m) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = j < m;
+  const size_t from = buf_off(false, 1 - cur, N) + j;
+  const int sp = valid ? (int)(S.meta[from] & 3u) : 0;
+  const bool g = valid && sp == EMS_GAMMA, ch = valid && sp != EMS_GAMMA;
+  const uint64_t mg = __ballot(g), mc = __ballot(ch);
+  unsigned long long old = 0;
+  if (lane == 0 && (mg | mc))
+    old = atomicAdd(ctr_line(P, kLAdmit),
+                    ((unsigned long long)__popcll(mc) << 32) | (unsigned long long)__popcll(mg));
+  old = __shfl(old, 0);
+  if (!valid) return;
+  const size_t to = buf_off(!g, cur, N) + (g ? lo32(old) + lanes_below(mg, lane)
+                                             : hi32(old) + lanes_below(mc, lane));
+  copy_track(S, from, to);
 }
 
 // Diagnostics: event slots that never finish (alive count far from zero) with a fixed
@@ -1624,6 +1878,8 @@ __global__ void k_slots_reset(Params P) {
   const_cast<double*>(P.scale)[e] = 0x1p40;
   for (int b = 0; b < P.nbins; ++b) P.tally[(size_t)e * P.nbins + b] = 0ull;
   for (int b = 0; b < kLedger; ++b) P.ledger[(size_t)e * kLedger + b] = 0ull;
+  if (P.ev_esc)
+    for (int b = 0; b < 3 * kGrid; ++b) P.ev_esc[(size_t)e * 3 * kGrid + b] = 0ull;
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
@@ -1727,9 +1983,9 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
 }
 
 hipError_t launch_iter_begin(unsigned long long* ctr, bool explicit_counts, uint32_t nG,
-                             uint32_t nC, hipStream_t s) {
+                             uint32_t nC, uint32_t j_iter, uint32_t* log, hipStream_t s) {
   hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(kNumLines * kLineWords), 0, s, ctr,
-                     explicit_counts ? 1 : 0, nG, nC);
+                     explicit_counts ? 1 : 0, nG, nC, j_iter, log);
   return hipGetLastError();
 }
 
@@ -1752,10 +2008,34 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
 
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
                              const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
-                             double* scale, double* e_row, hipStream_t s) {
+                             double* scale, double* e_row, uint32_t* g_row, hipStream_t s) {
   if (n_events == 0) return hipSuccess;
   hipLaunchKernelGGL(k_event_init, dim3(n_events), dim3(kBlock), 0, s, P, off, slots, T, sp, e_in,
-                     scale, e_row);
+                     scale, e_row, g_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_spill_hist(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
+                             uint32_t nC, unsigned long long* hist, hipStream_t s) {
+  const uint32_t n = nG + nC;
+  if (n == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>(blocks_for(n, 256), 2048);
+  hipLaunchKernelGGL(k_spill_hist, dim3(blocks), dim3(256), 0, s, P, S, N, cur, nG, nC, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_spill_split(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
+                              uint32_t nC, int bmin, uint32_t* cnt, hipStream_t s) {
+  const uint32_t blocks = blocks_for(nG, 256) + blocks_for(nC, 256);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spill_split, dim3(blocks), dim3(256), 0, s, P, S, N, cur, nG, nC, bmin, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_unspill(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t m,
+                          hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unspill, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, S, N, cur, m);
   return hipGetLastError();
 }
 
@@ -1794,31 +2074,41 @@ hipError_t launch_pool_dump(const Pool& p, const ems_track_soa& dst, uint32_t n,
 
 namespace ems {
 
-// Gather the tallies of n event slots into rows of (nbins + 5) doubles: deposits per
-// bin, then primary energy, escaped, killed, pair conversions, annihilations.
+// Gather the tallies of n event slots into rows of (nbins + kRowLedger) doubles:
+// deposits per bin, then primary energy, escaped, killed, pair conversions,
+// annihilations, track-steps of photons, electrons and positrons; with esc non-null
+// also the events' escape spectra (3 x kGrid counts per row).
 __global__ void k_gather_tallies(Params P, const uint32_t* slots, uint32_t n, const double* e_in,
-                                 double* out) {
+                                 double* out, unsigned long long* esc) {
   const uint32_t row = blockIdx.x;
   if (row >= n) return;
   const uint32_t s = slots[row];
   const double inv = 1.0 / P.scale[s];
-  const uint32_t w = (uint32_t)P.nbins + 5u;
+  const uint32_t w = (uint32_t)P.nbins + kRowLedger;
   for (int b = threadIdx.x; b < P.nbins; b += blockDim.x)
     out[(size_t)row * w + b] = (double)(long long)P.tally[(size_t)s * P.nbins + b] * inv;
+  if (esc && P.ev_esc)
+    for (int b = threadIdx.x; b < 3 * kGrid; b += blockDim.x)
+      esc[(size_t)row * 3 * kGrid + b] = P.ev_esc[(size_t)s * 3 * kGrid + b];
   if (threadIdx.x == 0) {
     double* L = out + (size_t)row * w + P.nbins;
+    const unsigned long long* G = P.ledger + (size_t)s * kLedger;
     L[0] = e_in[s];
-    L[1] = (double)(long long)P.ledger[(size_t)s * kLedger + 0] * inv;
-    L[2] = (double)(long long)P.ledger[(size_t)s * kLedger + 1] * inv;
-    L[3] = (double)P.ledger[(size_t)s * kLedger + 2];
-    L[4] = (double)P.ledger[(size_t)s * kLedger + 3];
+    L[1] = (double)(long long)G[0] * inv;
+    L[2] = (double)(long long)G[1] * inv;
+    L[3] = (double)G[2];
+    L[4] = (double)G[3];
+    L[5] = (double)G[kLedgerSteps];
+    L[6] = (double)G[kLedgerSteps + 1];
+    L[7] = (double)G[kLedgerSteps + 2];
   }
 }
 
 hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_t n,
-                                 const double* e_in, double* out, hipStream_t s) {
+                                 const double* e_in, double* out, unsigned long long* esc,
+                                 hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_tallies, dim3(n), dim3(128), 0, s, P, slots, n, e_in, out);
+  hipLaunchKernelGGL(k_gather_tallies, dim3(n), dim3(128), 0, s, P, slots, n, e_in, out, esc);
   return hipGetLastError();
 }
 
