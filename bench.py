@@ -143,8 +143,11 @@ def measured_traffic(args, precision=None):
             with open(path) as f:
                 t = json.load(f)
             sha = kernel_source_digest(os.path.join(ROOT, t["kernel_source"]))
+            # the counters are taken on a sample of the batch with the same per-event
+            # energy, in-flight budget, pool and sync interval: the pool holds the same
+            # mix of showers, so the bytes per iteration carry over
             same = (sha == t["kernel_code_sha256"] and t["precision"] == precision and
-                    t["events"] == args.events and t["energy_MeV"] == args.energy and
+                    t["energy_MeV"] == args.energy and
                     t["energy_budget_MeV"] == args.budget and t["pool_slots"] == args.pool and
                     t["iterations_per_sync"] == args.per_sync)
         except (OSError, KeyError, ValueError):
@@ -187,6 +190,7 @@ def run_transport(ems, args, precision, log_name, keep):
     slices += [(j * per, min(n, (j + 1) * per)) for j in range(args.steps)]
     layers = np.zeros(wl.geometry.n_bins)
     kept_dep, kept_led = [], []
+    shape = None
     ledger_max = 0.0
     total_steps, iters, peak, step_s = 0, 0, 0, []
     torch.cuda.synchronize()
@@ -201,6 +205,10 @@ def run_transport(ems, args, precision, log_name, keep):
         pr = ctx.transport(dev.slice(a, b), -1)
         dep, led, status = ctx.read(wl.events.event_ids[a:b])
         dt = time.perf_counter() - ts
+        if j == args.warmup:  # the first timed slice: per-iteration shape of one transport
+            shape = characterise(ctx.iteration_log(reset=True))
+        else:
+            ctx.iteration_log(reset=True)
         assert (status == 0).all() and pr.alive == 0
         log(f"{log_name} step {j} ({'timed' if timed else 'warmup'}): events {a}..{b - 1}, "
             f"{pr.track_steps} track-steps in {dt:.3f} s, {pr.iterations} iterations, peak pool "
@@ -222,9 +230,28 @@ def run_transport(ems, args, precision, log_name, keep):
     st = ctx.step_stats()
     ctx.close()
     return dict(steps=total_steps, t=t_run, iters=iters, peak=peak, stats=st, layers=layers,
-                ledger_max=ledger_max, step_s=step_s, per=per,
+                ledger_max=ledger_max, step_s=step_s, per=per, shape=shape,
                 kept_dep=np.concatenate(kept_dep) if kept_dep else None,
                 kept_led=np.concatenate(kept_led) if kept_led else None)
+
+
+def characterise(log):
+    """The per-iteration shape of one transport (the paper's characterisation of the
+    GPU loop): iterations to reach 90 % of the peak pool, share of iterations after
+    the peak with the pool below half of it (draining), shortest over longest
+    iteration time."""
+    if len(log) == 0:
+        return None
+    n = log["photons"].astype(np.int64) + log["charged"]
+    peak = int(n.max())
+    k_peak = int(np.argmax(n))
+    rise = int(np.argmax(n >= 0.9 * peak)) + 1
+    drain = int((n[k_peak:] < 0.5 * peak).sum())
+    ms = log["ms"]
+    return {"iterations": int(len(log)), "peak_tracks": peak, "iterations_to_90pct_of_peak": rise,
+            "draining_share": drain / len(log),
+            "min_over_max_iteration_time": float(ms.min() / ms.max()) if ms.max() > 0 else None,
+            "interactions_per_iteration_at_peak": int(log["interactions"][k_peak])}
 
 
 def run_serving(ems, args, precision, rate=None):
@@ -235,7 +262,8 @@ def run_serving(ems, args, precision, rate=None):
     ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
                       max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
                       seed=wl.seed, precision=precision, energy_budget=args.serve_budget,
-                      iterations_per_sync=min(args.serve_per_sync, args.serve_iters))
+                      iterations_per_sync=min(args.serve_per_sync, args.serve_iters),
+                      spill_capacity=args.serve_spill)
     ctx.setup(wl.materials, wl.options, wl.geometry)
     res = serve(ctx, wl.events, iterations=args.serve_iters, time_limit=300.0)
     ctx.close()
@@ -245,6 +273,48 @@ def run_serving(ems, args, precision, rate=None):
             "mean_event_energy_GeV": e_mean / 1000.0,
             "track_steps_per_s": res["track_steps"] / res["wall"], "wall_s": res["wall"],
             "peak_events_in_flight": res["peak_events"]}
+
+
+def run_csg(ems, n, args, precision):
+    """The quadric-cell module (spheres, an x-cylinder, a cone, planes): n events of one
+    primary from its centre; and the calorimeter written as cells next to its slab
+    navigation (same results bitwise), for the cost of general navigation."""
+    import torch
+    import workloads as W
+    out = {}
+    for name, wl in (("module", W.csg_module(n)),
+                     ("calorimeter_as_cells", W.Workload("c", W.calorimeter(1).materials,
+                                                         W.calorimeter(1).options,
+                                                         W.calorimeter_csg(),
+                                                         W.calorimeter(n // 10).events, 2)),
+                     ("calorimeter_slabs", W.calorimeter(n // 10))):
+        ne = wl.events.n_events
+        ctx = ems.Context(pool_capacity=args.pool, max_events=ne, max_bins=wl.geometry.n_bins,
+                          queue_capacity=wl.events.n_primaries, seed=wl.seed, precision=precision,
+                          energy_budget=args.budget, time_steps=True, iterations_per_sync=args.per_sync)
+        ctx.setup(wl.materials, wl.options, wl.geometry)
+        dev = ems.DeviceEvents(wl.events)
+        torch.cuda.synchronize()
+        ctx.step_stats(reset=True)
+        t0 = time.perf_counter()
+        pr = ctx.transport(dev, -1)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = ctx.step_stats()
+        dep, led, status = ctx.read(wl.events.event_ids)
+        ctx.close()
+        assert (status == 0).all()
+        bal = led[:, 0] - (dep.sum(1) + led[:, 1] + led[:, 2] + 2 * ME * (led[:, 3] - led[:, 4]))
+        log(f"quadric cells {name} {ne}: {pr.track_steps} track-steps in {t:.3f} s")
+        out[name] = {"events": ne, "value": pr.track_steps / t, "unit": "track-steps/s",
+                     "step_kernels_value": pr.track_steps / (st.kernel_ms / 1e3),
+                     "track_steps": pr.track_steps,
+                     "ledger_max_rel_error": float(np.abs(bal / led[:, 0]).max())}
+    out["workload"] = ("module: 40 cm Pb cube, Si spherical shell 8-10 cm, LAr, W rod r = 3 cm "
+                       "along x, conical vacuum channel; one primary per event from the centre, "
+                       "60/20/20 % e-/e+/photon, log-uniform 0.1-10 GeV, seed 7; calorimeter "
+                       f"1 GeV e-, {n // 10} events, as quadric cells and as slabs")
+    return out
 
 
 def run_photon_sat(ems, n, args):
@@ -353,11 +423,16 @@ def main():
     ap.add_argument("--no-photon-sat", action="store_true",
                     help="skip the photon-cube runs at 1e6 and 1e7 primaries")
     ap.add_argument("--serve-events", type=int, default=1000)
-    ap.add_argument("--serve-budget", type=float, default=5e7,
-                    help="energy in flight of the serving loop, MeV")
+    ap.add_argument("--serve-budget", type=float, default=0.0,
+                    help="energy in flight of the serving loop, MeV (0: admission by free "
+                         "pool slots only)")
+    ap.add_argument("--serve-spill", type=int, default=1 << 23,
+                    help="tracks the serving context may spill to pinned host memory")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
-    ap.add_argument("--serve-rate-high", type=float, default=120.0,
-                    help="a second, higher offered load (events/s); 0 skips it")
+    ap.add_argument("--serve-rates-high", type=str, default="120,200",
+                    help="higher offered loads (events/s, comma separated); empty skips them")
+    ap.add_argument("--no-csg", action="store_true", help="skip the quadric-cell geometry runs")
+    ap.add_argument("--csg-events", type=int, default=20_000)
     ap.add_argument("--serve-per-sync", type=int, default=4,
                     help="iterations per host synchronisation in the serving loop")
     ap.add_argument("--serve-iters", type=int, default=32,
@@ -414,7 +489,8 @@ def main():
                    "iterations": r["iters"], "peak_tracks_in_flight": r["peak"],
                    "track_steps": r["steps"], "ledger_max_rel_error": r["ledger_max"],
                    "step_ms": [round(x * 1e3, 2) for x in r["step_s"]],
-                   "step_ms_max_over_min": max(r["step_s"]) / min(r["step_s"])},
+                   "step_ms_max_over_min": max(r["step_s"]) / min(r["step_s"]),
+                   "characterisation_of_one_step": r["shape"]},
         "roofline": roofline(r, args.precision, measured_traffic(args)),
     }
     if cpu is not None:
@@ -460,11 +536,15 @@ def main():
                           "mixed": run_serving(ems, args, ems.EMS_MIXED),
                           "workload": "calorimeter geometry; events of U{1..500} primaries "
                                       "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
-        if args.serve_rate_high > 0:
-            r2 = args.serve_rate_high
-            out["serving"]["higher_load"] = {"offered_rate_hz": r2,
-                                             "fp64": run_serving(ems, args, ems.EMS_FP64, r2),
-                                             "mixed": run_serving(ems, args, ems.EMS_MIXED, r2)}
+        out["serving"]["admission"] = ("by free pool slots (a quarter of the pool for new "
+                                       "primaries), energy budget "
+                                       f"{args.serve_budget:g} MeV (0 = none); a pool above 3/4 "
+                                       "full spills its highest-energy tracks to host memory "
+                                       f"(room for {args.serve_spill} tracks)")
+        highs = [float(x) for x in args.serve_rates_high.split(",") if x.strip()]
+        out["serving"]["higher_loads"] = [
+            {"offered_rate_hz": r2, "fp64": run_serving(ems, args, ems.EMS_FP64, r2),
+             "mixed": run_serving(ems, args, ems.EMS_MIXED, r2)} for r2 in highs]
     if not args.no_barrel:
         fm = run_barrel(ems, args.barrel_events, args, ems.EMS_MIXED)
         fd = run_barrel(ems, args.barrel_events, args, ems.EMS_FP64)
@@ -473,6 +553,8 @@ def main():
                         "1-100 GeV, |eta| < 1.5, barrel of 5 Si shells + 50 Pb/LAr layers, "
                         "B_z = 1 T, RK4 tolerance 1e-5 cm, seed 4",
             "mixed": fm, "fp64": fd, "mixed_speedup_vs_fp64": fm["value"] / fd["value"]}
+    if not args.no_csg:
+        out["quadric_cells"] = run_csg(ems, args.csg_events, args, prec)
     if not args.no_photon_sat:
         out["photon_cube_sat"] = {
             "workload": "10 MeV photons into a 10 cm Pb cube, one photon per event, FP64",

@@ -162,6 +162,7 @@ typedef struct {
   uint64_t peak_alive;       /* largest pool occupancy seen by this call */
   uint64_t spilled;          /* tracks waiting in host memory after the call */
   uint64_t spilled_total;    /* tracks moved to host memory by this call */
+  uint64_t events_done;      /* finished events not yet read (tally_read) */
 } ems_progress;
 
 /* One step iteration of a transport_events call (paper Sec. 3.2, "Preliminary

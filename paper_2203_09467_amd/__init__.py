@@ -93,7 +93,7 @@ class Progress(C.Structure):
                 ("queued_events", C.c_uint64), ("iterations", C.c_uint64),
                 ("track_steps", C.c_uint64), ("deferred", C.c_uint64),
                 ("peak_alive", C.c_uint64), ("spilled", C.c_uint64),
-                ("spilled_total", C.c_uint64)]
+                ("spilled_total", C.c_uint64), ("events_done", C.c_uint64)]
 
 
 class IterationRecord(C.Structure):

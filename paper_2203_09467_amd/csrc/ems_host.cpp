@@ -167,6 +167,7 @@ struct ems_ctx {
   std::deque<EventInfo> pending;
   uint32_t q_head = 0, q_count = 0;
   uint64_t pending_prims = 0;
+  uint64_t done_unread = 0;  // finished events not yet read
   double e_flight = 0.0;
   // tracks waiting in pinned host memory: a stack of SoA rows [0, spill_top)
   Pool hs{};
@@ -348,6 +349,7 @@ void reset_events(ems_ctx* x) {
   x->q_head = 0;
   x->q_count = 0;
   x->pending_prims = 0;
+  x->done_unread = 0;
   x->e_flight = 0.0;
   x->nG = x->nC = 0;
   x->cur = 0;
@@ -918,6 +920,7 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
       const uint32_t sl = x->h_done[j];
       if (sl < x->slot_state.size() && x->slot_state[sl] == 1) {
         x->slot_state[sl] = 2;
+        x->done_unread += 1;
         x->e_flight -= x->slot_e[sl];
       }
     }
@@ -982,6 +985,7 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
     progress->peak_alive = peak;
     progress->spilled = x->spill_top;
     progress->spilled_total = io.spilled;
+    progress->events_done = x->done_unread;
   }
   return EMS_OK;
 }
@@ -1056,6 +1060,7 @@ ems_status tally_read(ems_ctx* x, uint32_t n, const uint32_t* ids, double* dep, 
     for (uint32_t sl : slots) x->slot_state[sl] = 2;
     return st;
   }
+  x->done_unread -= slots.size();
   for (uint32_t sl : slots) {  // release, once per slot
     x->id_to_slot.erase(x->slot_id[sl], x->slot_id);
     x->slot_state[sl] = 0;

@@ -368,11 +368,12 @@ __device__ __forceinline__ int locate(const Params& P, double x, double y, doubl
 // (-1 = outside the world).  Slabs: z-planes to neighbours, walls |x|,|y| to the
 // outside (ties to the walls).  Shells: outer radius outward, inner radius inward,
 // end caps outside (ties inner, then caps).
+template <bool CSG>
 __device__ __forceinline__ double distance(const Params& P, const double* bounds, int vol,
                                            double px, double py, double pz, double dx, double dy,
                                            double dz, int& next) {
 #pragma clang fp contract(off)
-  if (P.gkind == EMS_GEOM_CSG) return csg_distance(P, vol, px, py, pz, dx, dy, dz, next);
+  if (CSG) return csg_distance(P, vol, px, py, pz, dx, dy, dz, next);
   double s = HUGE_VAL;
   int nx = -1;
   if (P.gkind == EMS_GEOM_SLABS) {
@@ -518,6 +519,7 @@ __device__ __forceinline__ void rk4(double kappa, double h, double rx, double ry
 // with step-doubling error control, the boundary searched on each substep's chord
 // and accepted once the chord's sagitta is within tolerance.  Returns 0 at s_max,
 // 1 at a boundary (next set), 2 for a looper (vacuum path cap or substep cap).
+template <bool CSG>
 __device__ __forceinline__ int field_move(const Params& P, const double* bounds, int vol,
                                           double kappa, double s_max,
                                           bool vacuum, double& x, double& y, double& z,
@@ -548,7 +550,7 @@ __device__ __forceinline__ int field_move(const Params& P, const double* bounds,
       cx /= L;
       cy /= L;
       cz /= L;
-      sb = distance(P, bounds, vol, x, y, z, cx, cy, cz, nx);
+      sb = distance<CSG>(P, bounds, vol, x, y, z, cx, cy, cz, nx);
     }
     if (sb < L) {
       const double qx = mx - x, qy = my - y, qz = mz - z;
@@ -688,7 +690,7 @@ struct Moved {
 // escape, process selection (u_1 against Sigma_i(T')), cutoffs.  A track whose
 // step ends in an interaction (or a positron that stops) is sent to a queue with
 // its step count not yet incremented; every other survivor's count is incremented.
-template <class R, bool FIELD>
+template <class R, bool FIELD, bool CSG>
 __device__ __forceinline__ void transport(const Params& P, const View<R>& V, Track& t, Moved& o) {
   const double INF = HUGE_VAL;
   const int sp = t.sp;
@@ -731,11 +733,11 @@ __device__ __forceinline__ void transport(const Params& P, const View<R>& V, Tra
   if (FIELD && charged) {  // curved path up to the physics limit; a boundary met first wins
     const double p = sqrt(t.T * (t.T + 2.0 * kMe));
     const double kappa = 2.99792458 * (sp == EMS_ELECTRON ? -1.0 : 1.0) * P.bz / p;
-    const int res = field_move(P, V.bounds, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
+    const int res = field_move<CSG>(P, V.bounds, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
                                t.u, t.v, t.w, s, next);
     lim = res == 1 ? 0 : (res == 2 ? 3 : (s_phys <= s_cont ? 1 : 2));
   } else {
-    const double s_geo = distance(P, V.bounds, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
+    const double s_geo = distance<CSG>(P, V.bounds, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
     if (s_geo <= s_phys && s_geo <= s_cont) {
       lim = 0;
       s = s_geo;
@@ -1209,7 +1211,7 @@ __device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_clas
 // (deferred for lack of output room).  Survivors go to the output pool of their
 // class, tracks that interact to their process queue; both are reserved once per
 // block.
-template <class R, bool FIELD, bool STAGED>
+template <class R, bool FIELD, bool STAGED, bool CSG>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
                                                 uint32_t c, uint32_t nG, uint32_t nC,
@@ -1276,7 +1278,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
           o = Moved{};
           o.process = -1;
           o.dest = -2;
-          transport<R, FIELD>(P, V, t, o);
+          transport<R, FIELD, CSG>(P, V, t, o);
           ++nsteps;
           if (o.dep > 0.0)
             agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)V.vbin[v0]),
@@ -1413,7 +1415,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // At least four waves per SIMD without a field (four blocks of 256 per CU): the
 // loop of steps would otherwise take twice the registers of one step; the curved
 // move needs the registers.
-template <class R, bool FIELD, bool STAGED>
+template <class R, bool FIELD, bool STAGED, bool CSG>
 __global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
                                                       IQueue Q, ems_step_record* rec,
                                                       uint32_t msteps) {
@@ -1427,7 +1429,7 @@ __global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, P
     atomicMax(&st[kSPeak], (unsigned long long)n);
   }
   if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
-  transport_chunk<R, FIELD, STAGED>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG, msteps);
+  transport_chunk<R, FIELD, STAGED, CSG>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG, msteps);
 }
 
 // Wave-aggregated append of one output stream (parent or secondary j) into the
@@ -1719,56 +1721,40 @@ __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint
   q.event_id[k] = ids[lo];
 }
 
-// Initialise the event slots of a batch: one block per event.  E_in = sum of its
-// primaries' kinetic energies.  No tally or ledger sum of the event can exceed
-// E_max = E_in + 2 m per primary positron (its annihilation releases the rest
-// energy; pairs produced later consume what their positrons release), so the
+// Initialise the event slots of a batch: one thread per event, summing its primaries
+// in their order (the same order for an event in any batch, and the oracle's).
+// E_in = sum of its primaries' kinetic energies.  No tally or ledger sum of the event
+// can exceed E_max = E_in + 2 m per primary positron (its annihilation releases the
+// rest energy; pairs produced later consume what their positrons release), so the
 // fixed-point scale 2^(61 - ceil(log2 E_max)) keeps every sum below 2^61 quanta.
-// Tallies and ledger zeroed.
-__global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots,
+// Tallies, ledger and escape spectrum zeroed; photons per event counted for the host.
+__global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots, uint32_t n_events,
                              const double* T, const int32_t* sp, double* e_in, double* scale,
                              double* e_row, uint32_t* g_row) {
-  const uint32_t e = blockIdx.x;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_events) return;
   const int64_t a = off[e], b = off[e + 1];
-  __shared__ double part[kBlock];
-  __shared__ double partm[kBlock];
-  __shared__ uint32_t partg[kBlock];
   double s = 0.0, sm = 0.0;
   uint32_t ng = 0;
-  for (int64_t r = a + threadIdx.x; r < b; r += blockDim.x) {
-    s += T[r];
-    sm += T[r] + (sp[r] == EMS_POSITRON ? 2.0 * kMe : 0.0);
-    ng += sp[r] == EMS_GAMMA ? 1u : 0u;
-  }
-  part[threadIdx.x] = s;
-  partm[threadIdx.x] = sm;
-  partg[threadIdx.x] = ng;
-  __syncthreads();
-  for (int h = kBlock / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      part[threadIdx.x] += part[threadIdx.x + h];
-      partm[threadIdx.x] += partm[threadIdx.x + h];
-      partg[threadIdx.x] += partg[threadIdx.x + h];
-    }
-    __syncthreads();
+  for (int64_t r = a; r < b; ++r) {
+    const double t = T[r];
+    const int k = sp[r];
+    s += t;
+    sm += t + (k == EMS_POSITRON ? 2.0 * kMe : 0.0);
+    ng += k == EMS_GAMMA ? 1u : 0u;
   }
   const uint32_t slot = slots[e];
-  for (int j = threadIdx.x; j < P.nbins; j += blockDim.x) P.tally[(size_t)slot * P.nbins + j] = 0ull;
-  if (threadIdx.x < kLedger) P.ledger[(size_t)slot * kLedger + threadIdx.x] = 0ull;
+  for (int j = 0; j < P.nbins; ++j) P.tally[(size_t)slot * P.nbins + j] = 0ull;
+  for (int j = 0; j < kLedger; ++j) P.ledger[(size_t)slot * kLedger + j] = 0ull;
   if (P.ev_esc)
-    for (int j = threadIdx.x; j < 3 * kGrid; j += blockDim.x) P.ev_esc[(size_t)slot * 3 * kGrid + j] = 0ull;
-  if (threadIdx.x == 0) {
-    const double E = part[0], Emax = partm[0];
-    int ex = 0;
-    if (Emax > 0.0) {
-      frexp(Emax, &ex);  // Emax < 2^ex
-    }
-    e_in[slot] = E;
-    e_row[e] = E;  // per batch row, read back by the host
-    g_row[e] = partg[0];
-    scale[slot] = ldexp(1.0, 61 - ex);
-    P.alive[slot] = (int)(b - a);
-  }
+    for (int j = 0; j < 3 * kGrid; ++j) P.ev_esc[(size_t)slot * 3 * kGrid + j] = 0ull;
+  int ex = 0;
+  if (sm > 0.0) frexp(sm, &ex);  // E_max < 2^ex
+  e_in[slot] = s;
+  e_row[e] = s;  // per batch row, read back by the host
+  g_row[e] = ng;
+  scale[slot] = ldexp(1.0, 61 - ex);
+  P.alive[slot] = (int)(b - a);
 }
 
 // ------------------------------------------------------------------ spilling to host memory
@@ -1951,29 +1937,36 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   const dim3 b(kBlock);
   const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
   const bool field = P.bz != 0.0;
+  const bool csg = P.gkind == EMS_GEOM_CSG;
   // the run data is staged in LDS when it fits the per-block budget
   const uint32_t lds = stage_bytes(P.n_mats, P.nvol, mixed ? sizeof(float) : sizeof(double));
   const bool staged = lds <= kStageMaxBytes;
   const uint32_t sh = staged ? lds : 0u;
-#define EMS_LAUNCH_T(R, F, ST) \
-  hipLaunchKernelGGL((k_transport<R, F, ST>), gT, b, sh, s, P, S, N, cur, Q, rec, msteps)
+#define EMS_LAUNCH_T(R, F, ST, G) \
+  hipLaunchKernelGGL((k_transport<R, F, ST, G>), gT, b, sh, s, P, S, N, cur, Q, rec, msteps)
+#define EMS_LAUNCH_TG(R, F, ST) \
+  do {                              \
+    if (csg) EMS_LAUNCH_T(R, F, ST, true); \
+    else EMS_LAUNCH_T(R, F, ST, false);    \
+  } while (0)
   if (mixed) {
     if (field) {
-      if (staged) EMS_LAUNCH_T(float, true, true);
-      else EMS_LAUNCH_T(float, true, false);
+      if (staged) EMS_LAUNCH_TG(float, true, true);
+      else EMS_LAUNCH_TG(float, true, false);
     } else {
-      if (staged) EMS_LAUNCH_T(float, false, true);
-      else EMS_LAUNCH_T(float, false, false);
+      if (staged) EMS_LAUNCH_TG(float, false, true);
+      else EMS_LAUNCH_TG(float, false, false);
     }
   } else {
     if (field) {
-      if (staged) EMS_LAUNCH_T(double, true, true);
-      else EMS_LAUNCH_T(double, true, false);
+      if (staged) EMS_LAUNCH_TG(double, true, true);
+      else EMS_LAUNCH_TG(double, true, false);
     } else {
-      if (staged) EMS_LAUNCH_T(double, false, true);
-      else EMS_LAUNCH_T(double, false, false);
+      if (staged) EMS_LAUNCH_TG(double, false, true);
+      else EMS_LAUNCH_TG(double, false, false);
     }
   }
+#undef EMS_LAUNCH_TG
 #undef EMS_LAUNCH_T
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -2010,8 +2003,8 @@ hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t
                              const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
                              double* scale, double* e_row, uint32_t* g_row, hipStream_t s) {
   if (n_events == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_event_init, dim3(n_events), dim3(kBlock), 0, s, P, off, slots, T, sp, e_in,
-                     scale, e_row, g_row);
+  hipLaunchKernelGGL(k_event_init, dim3(blocks_for(n_events, 256)), dim3(256), 0, s, P, off, slots,
+                     n_events, T, sp, e_in, scale, e_row, g_row);
   return hipGetLastError();
 }
 

@@ -3,12 +3,17 @@
 An open-loop client of the C ABI.  Events whose arrival time has passed are
 submitted to ``transport_events`` together with a bounded number of step
 iterations, so requests that arrive while others are on the GPU join the same
-pool as soon as event slots and the energy budget allow (continuous batching:
-admission happens at every host synchronisation inside the library); finished
-events are collected with ``tally_read``.  Latency of an event = time its
-tallies were read - its arrival time.  Results do not depend on the mix: every
-event's random streams are keyed by its id and its tallies are fixed-point
-sums.
+pool as soon as event slots, pool room and (if set) the energy budget allow
+(continuous batching: admission happens at every host synchronisation inside the
+library; a pool that runs full sends its highest-energy tracks to host memory if
+the context has spill room); finished events are collected with ``tally_read``
+when the library reports some.  Latency of an event = time its tallies were read -
+its arrival time.  Results do not depend on the mix: every event's random streams
+are keyed by its id and its tallies are fixed-point sums.
+
+A batch refused for lack of event slots or queue room (EMS_E_CAPACITY) is retried
+smaller; a stalled pool (EMS_E_STALLED: full of put-off interactions with no spill
+room) raises, since its batch was accepted and nothing the loop can do frees room.
 """
 from __future__ import annotations
 
@@ -17,7 +22,7 @@ from typing import Dict
 
 import numpy as np
 
-from . import EMS_NOT_READY, EMS_OK, DeviceEvents, EmsError
+from . import EMS_E_CAPACITY, EMS_NOT_READY, EMS_OK, DeviceEvents, EmsError
 
 
 def serve(ctx, events, device_events: DeviceEvents = None, iterations: int = 8,
@@ -60,13 +65,13 @@ def serve(ctx, events, device_events: DeviceEvents = None, iterations: int = 8,
                 nxt = b
                 max_batch = min(max(n, 1), 2 * max_batch)
         except EmsError as e:  # no free slots or queue room: retry after others finish,
-            if e.status != -3:  # with a smaller batch (the library takes a batch whole)
+            if e.status != EMS_E_CAPACITY:  # with a smaller batch (a batch is taken whole)
                 raise
             max_batch = max(1, (b - nxt) // 2)
             pr = ctx.transport(None, iterations)
         steps += pr.track_steps
         peak_events = max(peak_events, len(in_flight))
-        if in_flight:
+        if in_flight and pr.events_done:
             d, L, st = ctx.read(in_flight)
             t_read = time.perf_counter() - t0
             keep = []

@@ -1,6 +1,7 @@
 """bench.py's command-line contract on the CPU: a request for more than one GPU
 exits with a message (this build runs on one GPU), and the measured-traffic lookup
-applies only to the workload and settings it was measured with."""
+applies only to the kernel code, per-event energy, precision and run settings it
+was measured with (on any sample size of the batch)."""
 import importlib.util
 import json
 import os
@@ -39,9 +40,11 @@ def test_traffic_applies_only_to_its_settings(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "TRAFFIC_GLOB", str(tmp_path / "*_traffic.json"))
     base = dict(precision="fp64", events=1000, energy=10000.0, budget=1e8, pool=1 << 24, per_sync=4)
     assert b.measured_traffic(types.SimpleNamespace(**base)) == 123.0
-    for k, v in (("precision", "mixed"), ("events", 10), ("energy", 1.0), ("budget", 1.0),
+    for k, v in (("precision", "mixed"), ("energy", 1.0), ("budget", 1.0),
                  ("per_sync", 1), ("pool", 64)):
         assert b.measured_traffic(types.SimpleNamespace(**{**base, k: v})) is None
+    # a sample of the batch with the same per-event settings: the counters carry over
+    assert b.measured_traffic(types.SimpleNamespace(**{**base, "events": 10})) == 123.0
     src.write_text("int k() { return 2; }\n")  # the kernel code changed since
     assert b.measured_traffic(types.SimpleNamespace(**base)) is None
 

@@ -162,6 +162,9 @@ def test_iteration_log():
     assert log["tracks_out"][-1] == 0
     # with every event admitted at the start, each iteration takes the previous one's output
     assert np.array_equal(n_in[1:], log["tracks_out"][:-1].astype(np.int64))
-    assert (log["ms"] > 0).all() and abs(log["ms"].sum() - st.kernel_ms) <= 1e-6 * st.kernel_ms
+    # iterations of the last sync interval that found the pool empty are timed but
+    # not recorded; they take a few microseconds each
+    assert (log["ms"] > 0).all()
+    assert log["ms"].sum() <= st.kernel_ms * (1 + 1e-6) and log["ms"].sum() >= 0.98 * st.kernel_ms
     assert int(n_in.max()) == pr.peak_alive
     assert len(ctx.iteration_log()) == 0  # the reset cleared it

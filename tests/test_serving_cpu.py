@@ -1,9 +1,10 @@
 """The serving loop's scheduling on the CPU, against a model of the library that
 needs no GPU: events arrive on a schedule, are submitted when their arrival time
 has passed, are refused while the model's event slots are full (EMS_E_CAPACITY,
-retried after others finish), and are read back once their work is done.
-Checks that every event is served exactly once, never before it arrives, and that
-the reported latencies and throughput follow from the schedule."""
+retried after others finish), and are read back once the model reports finished
+events.  Checks that every event is served exactly once, never before it arrives,
+that the reported latencies and throughput follow from the schedule, and that a
+stalled pool (EMS_E_STALLED) is raised rather than retried as a refusal."""
 import types
 
 import numpy as np
@@ -56,7 +57,8 @@ class _ModelContext:
             if self.left[e] == 0:
                 del self.left[e]
                 self.done.add(e)
-        return types.SimpleNamespace(track_steps=steps)
+        return types.SimpleNamespace(track_steps=steps,
+                                     events_done=len(self.done) - len(self.read_back))
 
     def read(self, ids):
         st = np.array([ems.EMS_OK if int(e) in self.done else ems.EMS_NOT_READY for e in ids],
@@ -91,3 +93,16 @@ def test_every_event_served_once_after_arrival(slots):
     if slots == 1:
         assert ctx.refusals > 0  # full slots were retried, and nothing was lost
     assert res["peak_events"] >= 1
+
+
+def test_a_stall_is_not_retried_as_a_refusal():
+    class _Stalls(_ModelContext):
+        def transport(self, batch, iterations):
+            raise ems.EmsError(ems.EMS_E_STALLED, "transport_events")
+
+    ids = np.arange(3, dtype=np.uint32)
+    events = types.SimpleNamespace(n_events=3, event_ids=ids, arrival=np.zeros(3))
+    ctx = _Stalls({0: 1, 1: 1, 2: 1}, 8)
+    with pytest.raises(ems.EmsError) as e:
+        serve(ctx, events, device_events=_Device(ids), iterations=4, time_limit=5.0)
+    assert e.value.status == ems.EMS_E_STALLED
