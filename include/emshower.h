@@ -206,6 +206,20 @@ size_t ems_workspace_bytes(const ems_config* cfg);
  * the one workspace.  EMS_E_ARG for an invalid cfg or a misaligned workspace,
  * EMS_E_CAPACITY for a workspace smaller than needed. */
 ems_status ems_create(const ems_config* cfg, void* d_workspace, size_t bytes, ems_ctx** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): as ems_create, but the
+ * workspace is the library's static device scratch of 256 MiB, which every GPU the
+ * library runs on holds until the process ends; the context uses the device that
+ * is current at this call.  Allocates no device or pinned host memory and creates
+ * no HIP object (host bookkeeping uses the C++ heap).  EMS_E_CAPACITY if
+ * ems_workspace_bytes(cfg) exceeds 256 MiB; EMS_E_ARG for an invalid cfg, a
+ * spill_capacity > 0 or EMS_FLAG_TIME_STEPS (both need allocations).  Every
+ * static context on one GPU shares the one scratch: creating a second one, or
+ * using two at once, races -- use one at a time per device (destroy, then create
+ * again).  The scratch keeps what the last context left; init_physics_tables,
+ * init_geometry and submission clear what must start at zero. */
+ems_status ems_create_static(const ems_config* cfg, ems_ctx** out);
 void ems_destroy(ems_ctx* ctx);
 const char* ems_last_error(void);
 

@@ -133,6 +133,7 @@ _P = C.POINTER
 _sigs = {
     "ems_workspace_bytes": (C.c_size_t, [_P(Config)]),
     "ems_create": (C.c_int, [_P(Config), C.c_void_p, C.c_size_t, _P(C.c_void_p)]),
+    "ems_create_static": (C.c_int, [_P(Config), _P(C.c_void_p)]),
     "ems_destroy": (None, [C.c_void_p]),
     "ems_last_error": (C.c_char_p, []),
     "init_physics_tables": (C.c_int, [C.c_void_p, _P(Material), C.c_int32, _P(PhysicsOptions),
@@ -181,6 +182,13 @@ def workspace_bytes(cfg: Config) -> int:
 def create(cfg: Config, workspace_ptr: int, nbytes: int) -> C.c_void_p:
     h = C.c_void_p()
     _check(_lib.ems_create(C.byref(cfg), C.c_void_p(workspace_ptr), nbytes, C.byref(h)), "ems_create")
+    return h
+
+
+def create_static(cfg: Config) -> C.c_void_p:
+    """A context over the library's static device scratch (no allocation)."""
+    h = C.c_void_p()
+    _check(_lib.ems_create_static(C.byref(cfg), C.byref(h)), "ems_create_static")
     return h
 
 

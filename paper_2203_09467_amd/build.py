@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libemshower.so")
-SOURCES = ["ems_kernels.hip", "ems_host.cpp", "ems_tables.cpp"]
+SOURCES = ["ems_kernels.hip", "ems_host.cpp", "ems_tables.cpp", "ems_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
