@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GAMMA, ELECTRON, POSITRON = 0, 1, 2
 NGRID = 200
+LIFE_BINS = 17
 
 
 class Material(C.Structure):
@@ -31,7 +32,7 @@ class Options(C.Structure):
                 ("ionisation", C.c_int), ("brems", C.c_int), ("annihilation", C.c_int),
                 ("charged_local", C.c_int), ("continuous_loss", C.c_int),
                 ("step_alpha", C.c_double), ("step_rfinal", C.c_double),
-                ("max_steps", C.c_uint32)]
+                ("max_steps", C.c_uint32), ("msc", C.c_int)]
 
 
 class Geometry(C.Structure):
@@ -47,7 +48,7 @@ class Track(C.Structure):
     _fields_ = [("species", C.c_int), ("x", C.c_double), ("y", C.c_double), ("z", C.c_double),
                 ("u", C.c_double), ("v", C.c_double), ("w", C.c_double), ("T", C.c_double),
                 ("nlam", C.c_double), ("key", C.c_uint32 * 3), ("event", C.c_uint32),
-                ("nstep", C.c_uint32), ("vol", C.c_int)]
+                ("nstep", C.c_uint32), ("vol", C.c_int), ("vac_caps", C.c_uint32)]
 
 
 class StepResult(C.Structure):
@@ -80,7 +81,7 @@ def lib() -> C.CDLL:
             "or_moller_dsigma": (d, [d, d]), "or_bhabha_sigma": (d, [d, d]),
             "or_bhabha_dsigma": (d, [d, d]), "or_heitler_sigma": (d, [d, d]),
             "or_heitler_dsigma": (d, [d, d, d]), "or_scol": (d, [i, d, d, d, d]),
-            "or_radiation_length": (d, [d, d, d]),
+            "or_radiation_length": (d, [d, d, d]), "or_msc_theta0": (d, [d, d, d]),
             "or_accept_moller": (d, [d, d]), "or_accept_bhabha": (d, [d, d]),
             "or_accept_heitler": (d, [d, d]), "or_accept_kn": (d, [d, d]),
             "or_sample_kn": (i, [d, P(d), i, P(d), P(d)]),
@@ -112,7 +113,9 @@ def lib() -> C.CDLL:
             "or_rk4": (None, [d, d, P(d), P(d), P(d), P(d)]),
             "or_field_move": (i, [C.c_void_p, i, d, d, i, P(d), P(d), P(d), P(i)]),
             "or_run_batch": (i, [C.c_void_p, u32, i, P(u32), P(C.c_int64), P(i), P(d), P(d),
-                                 P(d), P(d), P(d), P(C.c_int64), P(C.c_int64), C.c_void_p]),
+                                 P(d), P(d), P(d), P(C.c_int64), P(C.c_int64), C.c_void_p,
+                                 C.c_void_p]),
+            "or_life_bin": (i, [C.c_long]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -283,6 +286,7 @@ class World:
             t.event = int(st["event"][i])
             t.nstep = int(st["nstep"][i])
             t.vol = int(st["vol"][i])
+            t.vac_caps = int(st["vcap"][i]) if "vcap" in st else 0
             if L.or_step(self.h, seed, C.byref(t), C.byref(r)) != 0:
                 raise RuntimeError("oracle step failed")
             c = StepResult()
@@ -290,10 +294,11 @@ class World:
             out.append(c)
         return out
 
-    def run_events(self, seed: int, ev, esc_hist: bool = False):
+    def run_events(self, seed: int, ev, esc_hist: bool = False, life_hist: bool = False):
         """Transport a workloads.Events batch; returns dict with dep (n_events x n_bins),
         ledger (n_events x 5: e_in, escaped, killed, n_pair, n_annih), steps[3], tracks[3]
-        and optionally the escape histogram (3 x 200)."""
+        and optionally the escape histogram (3 x 200) and the steps-per-track
+        histogram (3 x LIFE_BINS)."""
         L = lib()
         ne = ev.n_events
         dep = np.zeros((ne, self.n_bins), np.float64)
@@ -301,6 +306,7 @@ class World:
         steps = np.zeros(3, np.int64)
         tracks = np.zeros(3, np.int64)
         hist = np.zeros((3, NGRID), np.float64) if esc_hist else None
+        lh = np.zeros((3, LIFE_BINS), np.float64) if life_hist else None
         ids = np.ascontiguousarray(ev.event_ids, np.uint32)
         off = np.ascontiguousarray(ev.offsets, np.int64)
         sp = np.ascontiguousarray(ev.species, np.int32)
@@ -311,12 +317,15 @@ class World:
                             _ptr(sp, C.c_int), _ptr(T, C.c_double), _ptr(pos, C.c_double),
                             _ptr(d, C.c_double), _ptr(dep, C.c_double), _ptr(ledger, C.c_double),
                             _ptr(steps, C.c_int64), _ptr(tracks, C.c_int64),
-                            None if hist is None else hist.ctypes.data)
+                            None if hist is None else hist.ctypes.data,
+                            None if lh is None else lh.ctypes.data)
         if rc != 0:
             raise RuntimeError("oracle transport failed")
         res = dict(dep=dep, ledger=ledger, steps=steps, tracks=tracks)
         if hist is not None:
             res["esc_hist"] = hist
+        if lh is not None:
+            res["life_hist"] = lh
         return res
 
 

@@ -18,17 +18,19 @@
  *     from the chord) is within the tolerance -- position on the chord at the
  *     boundary, path length the same fraction of h, direction from one RK4 step of
  *     that length -- otherwise h shrinks by that fraction and the substep is redone;
- *   - a step ends at the physics limit (discrete or continuous) or, in vacuum,
- *     after 1000 cm of path; a track that reaches that vacuum cap or needs more
- *     than 10^4 substeps in one step is a looper and is killed.
+ *   - a step in matter ends at the physics limit (discrete or continuous) or the
+ *     boundary; one needing more than 10^4 substeps is a looper and is killed;
+ *   - a step in vacuum (no physics limit) ends at the boundary or after 256
+ *     substeps; the step that ends the 40th such capped step in a row is a
+ *     looper (or_step keeps the count).
  */
 #include <math.h>
 
 #include "oracle_internal.h"
 
 #define OR_FIELD_MAXSUB 10000
+#define OR_FIELD_VACSUB 256
 #define OR_FIELD_HMIN 1.0e-9
-#define OR_FIELD_LVAC 1000.0
 
 double or_field_kappa(double q, double bz, double p) { return 2.99792458 * q * bz / p; }
 
@@ -79,15 +81,17 @@ static void normalise(double v[3]) {
 
 /* Move (r, d) in volume vol along the curved path for at most s_max (may be
  * infinite).  Returns 0 when s_max was reached, 1 at a boundary (*next set), 2 for
- * a looper; *s_out = path length travelled. */
+ * a looper in matter, 3 when a vacuum step used its 256 substeps; *s_out = path
+ * length travelled. */
 int or_field_move(const or_world* w, int vol, double kappa, double s_max, int vacuum, double r[3],
                   double d[3], double* s_out, int* next) {
   const double tol = w->geo.tol;
-  const double limit = vacuum ? fmin(s_max, OR_FIELD_LVAC) : s_max;
+  const double limit = s_max;
   double travelled = 0.0;
   double h = fabs(kappa) > 0.0 ? fmin(limit, 1.0 / fabs(kappa)) : limit;
   *next = OR_OUTSIDE;
-  for (int nsub = 0; nsub < OR_FIELD_MAXSUB; ++nsub) {
+  const int max_sub = vacuum ? OR_FIELD_VACSUB : OR_FIELD_MAXSUB;
+  for (int nsub = 0; nsub < max_sub; ++nsub) {
     double hh = fmin(h, limit - travelled);
     double rf[3], df[3], rm[3], dm[3], r2[3], d2[3];
     or_rk4(kappa, hh, r, d, rf, df);
@@ -142,10 +146,10 @@ int or_field_move(const or_world* w, int vol, double kappa, double s_max, int va
     travelled += hh;
     if (travelled >= limit) {
       *s_out = travelled;
-      return limit < s_max ? 2 : 0;
+      return 0;
     }
     h = err < tol / 32.0 ? 2.0 * hh : hh;
   }
   *s_out = travelled;
-  return 2;
+  return vacuum ? 3 : 2;
 }

@@ -38,7 +38,8 @@ enum { OR_GAMMA = 0, OR_ELECTRON = 1, OR_POSITRON = 2 };
 enum { OR_NGRID = 200, OR_NQ = 4, OR_MAXMAT = 8 };
 enum { OR_GEOM_SLABS = 0, OR_GEOM_CYLINDERS = 1, OR_GEOM_CSG = 2 };
 enum { OR_OUTSIDE = -1 };
-enum { OR_LIM_GEO = 0, OR_LIM_PHYS = 1, OR_LIM_CONT = 2, OR_LIM_LOOPER = 3 };
+enum { OR_LIM_GEO = 0, OR_LIM_PHYS = 1, OR_LIM_CONT = 2, OR_LIM_LOOPER = 3, OR_LIM_VACCAP = 4 };
+enum { OR_VAC_CAPS = 40 }; /* consecutive substep-capped vacuum steps that make a looper */
 
 typedef struct {
   double Z, A, density, mean_excitation; /* mean_excitation in MeV; density 0 = vacuum */
@@ -53,6 +54,7 @@ typedef struct {
   double step_alpha;         /* continuous step limit: fraction of residual range */
   double step_rfinal;        /* cm: residual range below which a track ranges out */
   uint32_t max_steps;        /* looper cap per track */
+  int msc;                   /* 1: Gaussian multiple-scattering deflection of e-/e+ steps */
 } or_options;
 
 typedef struct {
@@ -82,6 +84,7 @@ typedef struct {
   uint32_t event;    /* event slot */
   uint32_t nstep;    /* steps taken so far */
   int vol;           /* current volume */
+  uint32_t vac_caps; /* field: vacuum steps in a row that ended on the substep cap */
 } or_track;
 
 typedef struct {
@@ -126,6 +129,7 @@ double or_heitler_sigma(double Z, double T);          /* e+ annihilation in flig
 double or_heitler_dsigma(double Z, double T, double eps);
 double or_scol(int positron, double n_el, double I, double T, double cut); /* restricted, MeV/cm */
 double or_radiation_length(double Z, double A, double density);           /* cm */
+double or_msc_theta0(double T, double x, double X0); /* Highland width, rad */
 
 /* ---- samplers: draws are u[0], u[1], ... ; returns number of draws consumed */
 int or_sample_kn(double E, const double* u, int nu, double* eps, double* cost);
@@ -161,7 +165,8 @@ int or_csg_side(const double* q, const double p[3], const double d[3]);
 double or_csg_exit(const double* q, const double p[3], const double d[3], int sigma);
 
 /* Charged tracks in the uniform field B_z: curvature, one RK4 step, and the curved
- * move of a step (returns 0 at s_max, 1 at a boundary, 2 for a looper). */
+ * move of a step (returns 0 at s_max, 1 at a boundary, 2 for a looper in matter,
+ * 3 at the substep cap of a vacuum step). */
 double or_field_kappa(double q, double bz, double p);
 void or_rk4(double kappa, double h, const double r[3], const double d[3], double ro[3],
             double dout[3]);
@@ -181,6 +186,7 @@ typedef struct {
   long steps[3];         /* track-steps by species */
   long tracks[3];        /* tracks created (primaries included) by species */
   double* esc_hist;      /* 3 * OR_NGRID counts of escaping energy bins, or NULL */
+  double* life_hist;     /* 3 * OR_LIFE_BINS tracks ended, by species and steps taken, or NULL */
   double e_in;
 } or_event_tally;
 
@@ -189,10 +195,16 @@ int or_run_event(const or_world* w, uint32_t seed, uint32_t event_id, int n_prim
                  const int* species, const double* T, const double* pos, const double* dir,
                  or_event_tally* tally);
 
+/* Steps-per-track distribution (Sec. 3.2, the steps each track takes, compared between
+ * codes): bin 0 holds tracks that took no step, bin b >= 1 tracks whose step count n has
+ * 2^(b-1) <= n < 2^b, the last bin everything from 2^(OR_LIFE_BINS-2) up. */
+#define OR_LIFE_BINS 17
+int or_life_bin(long n);
+
 int or_run_batch(const or_world* w, uint32_t seed, int n_events, const uint32_t* event_ids,
                  const int64_t* offsets, const int* species, const double* T, const double* pos,
                  const double* dir, double* dep, double* ledger, int64_t* steps, int64_t* tracks,
-                 double* esc_hist);
+                 double* esc_hist, double* life_hist);
 
 #ifdef __cplusplus
 }

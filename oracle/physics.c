@@ -436,3 +436,17 @@ double or_cut_electron(const or_world* w, int mat) { return w->mat[mat].Tc; }
 double or_cut_gamma(const or_world* w, int mat) { return w->mat[mat].kc; }
 double or_range_at_cut(const or_world* w, int mat, int species) { return w->mat[mat].Rtrk[species]; }
 double or_material_X0(const or_world* w, int mat) { return w->mat[mat].X0; }
+
+/* Highland's fit to the width of the projected angular distribution of multiple
+ * Coulomb scattering (V. L. Highland, NIM 129 (1975) 497; G. R. Lynch and O. I. Dahl,
+ * NIM B58 (1991) 6): theta0 = 13.6 MeV / (beta c p) sqrt(x/X0) [1 + 0.038 ln(x / (X0 beta^2))]
+ * for a singly charged particle of kinetic energy T over a path x; 0 where the
+ * bracket is not positive (paths far below the fit's range). */
+double or_msc_theta0(double T, double x, double X0) {
+  const double p = sqrt(T * (T + 2.0 * OR_ME));
+  const double beta = p / (T + OR_ME);
+  const double r = x / X0;
+  const double bracket = 1.0 + 0.038 * log(r / (beta * beta));
+  if (!(r > 0.0) || !(bracket > 0.0)) return 0.0;
+  return 13.6 / (beta * p) * sqrt(r) * bracket;
+}

@@ -28,6 +28,7 @@
 
 #define OR_MAXTRIAL 1000
 #define OR_REST_STEP 0xFFFFFFFFu
+#define OR_MSC_DRAW 0x40000000 /* first of the two draws of a step's scattering angle */
 
 /* ------------------------------------------------------------ geometry */
 
@@ -420,6 +421,7 @@ static void add_track(emitter* e, int species, double T, const double dir[3], co
   t->w = dir[2];
   t->nlam = -1.0;
   t->nstep = 0;
+  t->vac_caps = 0;
   t->key[0] = key[0];
   t->key[1] = key[1];
   t->key[2] = key[2];
@@ -522,7 +524,9 @@ int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result
                                   &next);
     if (res == 1) lim = OR_LIM_GEO;
     else if (res == 2) lim = OR_LIM_LOOPER;
+    else if (res == 3) lim = t.vac_caps + 1 >= OR_VAC_CAPS ? OR_LIM_LOOPER : OR_LIM_VACCAP;
     else lim = s_phys <= s_cont ? OR_LIM_PHYS : OR_LIM_CONT;
+    t.vac_caps = res == 3 ? t.vac_caps + 1 : 0;
   } else {
     const double s_geo = or_distance(w, t.vol, pos, dir, &next);
     if (s_geo <= s_phys && s_geo <= s_cont) {
@@ -560,6 +564,21 @@ int or_step(const or_world* w, uint32_t seed, const or_track* in, or_step_result
     }
   }
   if (lim != OR_LIM_PHYS && sigtot > 0.0) t.nlam -= s * sigtot;
+
+  /* multiple scattering of an e-/e+ still moving in matter at the end of the step */
+  if (w->opt.msc && charged && in_matter && s > 0.0 && !stopped && T1 >= w->opt.tracking_cut &&
+      lim != OR_LIM_LOOPER && !(lim == OR_LIM_GEO && next == OR_OUTSIDE)) {
+    const double th0 = or_msc_theta0(t.T, s, m->X0);
+    st.pos = OR_MSC_DRAW;
+    const double ua = next_u(&st), ub = next_u(&st);
+    double th = th0 * sqrt(-2.0 * log(ua));
+    if (th > OR_PI) th = OR_PI;
+    double nd[3];
+    rotate(dir, cos(th), 2.0 * OR_PI * ub, nd);
+    dir[0] = nd[0];
+    dir[1] = nd[1];
+    dir[2] = nd[2];
+  }
 
   /* post-step state of the parent */
   or_track post = t;
@@ -733,6 +752,15 @@ static int esc_bin(const or_world* w, double E) {
   return (int)floor(t);
 }
 
+int or_life_bin(long n) {
+  int b = 0;
+  while (n > 0 && b < OR_LIFE_BINS - 1) {  /* b = number of binary digits of n */
+    n >>= 1;
+    b += 1;
+  }
+  return b;
+}
+
 int or_run_event(const or_world* w, uint32_t seed, uint32_t event_id, int n_prim,
                  const int* species, const double* T, const double* pos, const double* dir,
                  or_event_tally* tl) {
@@ -747,6 +775,7 @@ int or_run_event(const or_world* w, uint32_t seed, uint32_t event_id, int n_prim
     if (vol == OR_OUTSIDE) {
       tl->esc += T[i];
       if (tl->esc_hist) tl->esc_hist[species[i] * OR_NGRID + esc_bin(w, T[i])] += 1.0;
+      if (tl->life_hist) tl->life_hist[species[i] * OR_LIFE_BINS + 0] += 1.0;
       continue;
     }
     if (n == cap) {
@@ -806,7 +835,10 @@ int or_run_event(const or_world* w, uint32_t seed, uint32_t event_id, int n_prim
         stack[n++] = r.out[i];
         tl->tracks[r.out[i].species] += 1;
       }
-      if (!r.parent_alive) break;
+      if (!r.parent_alive) {
+        if (tl->life_hist) tl->life_hist[t.species * OR_LIFE_BINS + or_life_bin((long)t.nstep + 1)] += 1.0;
+        break;
+      }
       t = r.out[0];
     }
   }
@@ -817,11 +849,12 @@ int or_run_event(const or_world* w, uint32_t seed, uint32_t event_id, int n_prim
 /* Run events [0, n_events) of a batch; primaries of event e are rows
  * offsets[e] .. offsets[e+1]-1.  dep is n_events x n_bins (accumulated),
  * ledger is n_events x 5 (e_in, escaped, killed, n_pair, n_annih),
- * steps/tracks are per species (accumulated), esc_hist is 3 x OR_NGRID or NULL. */
+ * steps/tracks are per species (accumulated), esc_hist is 3 x OR_NGRID or NULL,
+ * life_hist is 3 x OR_LIFE_BINS or NULL (both accumulated). */
 int or_run_batch(const or_world* w, uint32_t seed, int n_events, const uint32_t* event_ids,
                  const int64_t* offsets, const int* species, const double* T, const double* pos,
                  const double* dir, double* dep, double* ledger, int64_t* steps, int64_t* tracks,
-                 double* esc_hist) {
+                 double* esc_hist, double* life_hist) {
   const int nb = w->geo.n_bins;
   for (int e = 0; e < n_events; ++e) {
     const int64_t a = offsets[e], b = offsets[e + 1];
@@ -829,6 +862,7 @@ int or_run_batch(const or_world* w, uint32_t seed, int n_events, const uint32_t*
     memset(&tl, 0, sizeof(tl));
     tl.dep_bins = dep + (size_t)e * (size_t)nb;
     tl.esc_hist = esc_hist;
+    tl.life_hist = life_hist;
     if (or_run_event(w, seed, event_ids[e], (int)(b - a), species + a, T + a, pos + 3 * a,
                      dir + 3 * a, &tl) != 0)
       return -1;

@@ -1,7 +1,8 @@
 """Pins of the oracle's charged-track propagation in a uniform field (CPU): the RK4
 path against the analytic helix, the boundary crossing against the exact
-helix-cylinder intersection, the looper rule, and energy conservation of barrel
-events with the field on."""
+helix-cylinder intersection, the substep cap of a vacuum step and the looper rule
+(forty capped vacuum steps in a row), and energy conservation of barrel events with
+the field on."""
 import math
 
 import numpy as np
@@ -41,7 +42,8 @@ def test_rk4_path_follows_helix(orc, p_mev, theta):
     w = _vacuum_world(orc, [0.0, 1.0e6])
     kappa = orc.closed("field_kappa", -1.0, 1.0, p_mev)
     d0 = [math.sin(theta), 0.0, math.cos(theta)]
-    st, s, pos, d, nx = w.field_move(0, kappa, 400.0, 1, [0.0, 0.0, 0.0], d0)
+    # the matter rules (no substep cap below 10^4): the path runs to s_max
+    st, s, pos, d, nx = w.field_move(0, kappa, 400.0, 0, [0.0, 0.0, 0.0], d0)
     assert st == 0 and s == pytest.approx(400.0, rel=1e-12)
     pe, de = _helix([0.0, 0.0, 0.0], d0, kappa, s)
     assert np.abs(np.array(pos) - pe).max() < 2e-3  # accumulated from substeps of <= 1e-5 cm
@@ -68,12 +70,27 @@ def test_boundary_crossing_on_cylinder(orc, p_mev, theta, phi):
     assert np.abs(np.array(d) - dt).max() < 1e-4
 
 
-def test_looper_is_stopped(orc):
+def test_vacuum_step_cap_and_looper(orc):
     w = _vacuum_world(orc, [0.0, 50.0, 100.0])
     kappa = orc.closed("field_kappa", -1.0, 1.0, math.sqrt(1.0 * (1.0 + 2 * ME)))
     st, s, pos, d, nx = w.field_move(0, kappa, 1.0e9, 1, [10.0, 0.0, 0.0], [0.0, 1.0, 0.0])
-    assert st == 2  # a 1 MeV electron circling in vacuum never meets a surface
+    assert st == 3  # a 1 MeV electron circling in vacuum: the step ends on its substep cap
     assert math.hypot(pos[0], pos[1]) < 11.0
+    # in the step: capped vacuum steps go on (limiter 4) until the 40th in a row,
+    # which kills the track (limiter 3); a boundary resets the count
+    wl = W.barrel(1)
+    wo = orc.World(wl.materials, wl.options, wl.geometry)
+    n = 3
+    st_in = dict(species=np.full(n, W.ELECTRON, np.int32), energy=np.full(n, 1.0),
+                 vol=np.zeros(n, np.int32), pos=np.array([[1.0, 0, 0]] * n),
+                 dir=np.array([[0, 1.0, 0]] * n), nlam=np.full(n, 1.0),
+                 key=np.arange(3 * n, dtype=np.uint32).reshape(n, 3), nstep=np.zeros(n, np.uint32),
+                 event=np.zeros(n, np.uint32), vcap=np.array([0, 38, 39], np.uint32))
+    res = wo.step_tracks(wl.seed, st_in)
+    assert [r.limiter for r in res] == [4, 4, 3]
+    assert res[0].parent_alive and res[0].out[0].vac_caps == 1
+    assert res[1].parent_alive and res[1].out[0].vac_caps == 39
+    assert not res[2].parent_alive and res[2].killed == 1.0
 
 
 def test_barrel_events_conserve_energy(orc):

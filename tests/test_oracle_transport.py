@@ -96,6 +96,42 @@ def test_energy_conservation_photon_cube(orc):
     assert r["esc_hist"].sum() > 0
 
 
+def _life_bounds(life):
+    """Per species, the least and greatest total step count a steps-per-track histogram allows."""
+    b = np.arange(life.shape[1])
+    lo = np.where(b == 0, 0, 2.0 ** (b - 1))
+    hi = np.where(b == 0, 0, 2.0 ** b - 1)
+    life = np.asarray(life, np.float64)
+    top = np.where(life[:, -1] > 0, np.inf, 0.0)  # the last bin has no upper end
+    return life @ lo, life[:, :-1] @ hi[:-1] + top
+
+
+def test_life_bins_are_bit_lengths(orc):
+    L = orc.lib()
+    for n in list(range(0, 70)) + [2 ** k + d for k in range(6, 20) for d in (-1, 0, 1)]:
+        assert L.or_life_bin(n) == min(int(n).bit_length(), orc.LIFE_BINS - 1), n
+
+
+@pytest.mark.parametrize("name", ["photon_cube", "calorimeter"])
+def test_steps_per_track_histogram(orc, name):
+    """Every track ends once; only a primary born outside takes no step; the histogram
+    bounds each species' step count."""
+    wl = W.photon_cube(500) if name == "photon_cube" else W.calorimeter(6)
+    ev = wl.events
+    # move a tenth of the primaries outside the world, heading away from it
+    out = np.arange(ev.n_primaries) % 10 == 3
+    ev.pos[out] = [0.0, 0.0, -1e4]
+    ev.dir[out] = [0.0, 0.0, -1.0]
+    r = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, ev, life_hist=True)
+    life = r["life_hist"]
+    assert np.array_equal(life.sum(1), r["tracks"].astype(np.float64))
+    born_out = np.bincount(ev.species[out], minlength=3)
+    assert np.array_equal(life[:, 0], born_out.astype(np.float64))
+    lo, hi = _life_bounds(life)
+    assert (lo <= r["steps"]).all() and (r["steps"] <= hi).all(), (lo, r["steps"], hi)
+    assert life[:, 1:].sum() > 0
+
+
 def test_energy_conservation_calorimeter(orc):
     wl = W.calorimeter(40)
     w = orc.World(wl.materials, wl.options, wl.geometry)

@@ -57,6 +57,7 @@ class Options:
     step_alpha: float = 0.2
     step_rfinal: float = 0.01
     max_steps: int = 1 << 16
+    msc: int = 0  # Gaussian multiple-scattering deflection of e-/e+ (not in the benchmark configs)
 
 
 @dataclasses.dataclass
