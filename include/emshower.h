@@ -65,13 +65,21 @@ typedef struct {
   uint32_t queue_capacity;  /* primaries waiting for admission */
   uint32_t seed;            /* random stream seed of the run */
   ems_precision precision;  /* arithmetic of cross sections, interpolation and sampling */
-  double energy_budget;     /* MeV of primary energy admitted at once; <= 0: unlimited */
+  double energy_budget;     /* MeV: whole events are admitted while the kinetic energy of
+                               the tracks in the pool (measured on the device at each
+                               host synchronisation) plus that of the primaries admitted
+                               since stays within it; <= 0: unlimited */
   uint32_t flags;           /* EMS_FLAG_* */
   uint32_t iterations_per_sync; /* step iterations enqueued per host synchronisation
                                    (admission and completion bookkeeping happen at
                                    synchronisations); 0 = 8, at most 32 */
   uint32_t spill_capacity;  /* tracks that may wait in pinned host memory when the pool
-                               runs full (88 B each, allocated by ems_create); 0 = none */
+                               runs full (108 B each, allocated by ems_create); 0 = none */
+  uint32_t field_substeps;  /* with a field: curved-move substeps a charged track may take
+                               per step of one launch (a launch takes up to 4 steps, 32 for
+                               a small pool); a move that needs more is suspended and
+                               continued by the next launch exactly where it stood, so
+                               results do not depend on it.  0 = 4, at most 1024 */
 } ems_config;
 
 /* flags: time every step-kernel launch with HIP events on the launch stream */
@@ -105,6 +113,9 @@ typedef struct {
   double step_alpha;      /* continuous step limit: fraction of residual range */
   double step_rfinal;     /* cm: residual range below which a track ranges out */
   uint32_t max_steps;     /* per-track step cap (loopers); energy goes to "killed" */
+  int32_t msc;            /* 1: multiple-scattering deflection of e-/e+ steps in matter
+                             (Gaussian, Highland width; paper Table "Current status of
+                             Celeritas EM physics" lists multiple scattering in progress) */
 } ems_physics_options;
 
 /* Volumes are slabs between z-planes (lateral walls |x| <= half_x, |y| <= half_y),
@@ -181,7 +192,8 @@ typedef struct {
 typedef struct {
   double dep, esc, killed, step_len;
   int32_t limiter;  /* 0 boundary, 1 discrete interaction, 2 continuous-loss limit,
-                       3 looper in the field (killed) */
+                       3 looper in the field (killed), 4 a field step in vacuum that
+                       ended on its substep cap (the track goes on) */
   int32_t process;  /* selected process, -1 none */
   int32_t n_pair, n_annih;
   int32_t n_out;    /* outputs: surviving parent + secondaries */
@@ -193,6 +205,8 @@ typedef struct {
   double *x, *y, *z, *u, *v, *w, *T, *nlam;
   uint32_t *k0, *k1, *k2, *event, *nstep;
   int32_t *species, *vol;
+  uint32_t* vcap;   /* field steps in vacuum that ended on their substep cap, in a row
+                       (0 .. 39); may be NULL (all 0 / not written) */
 } ems_track_soa;
 
 /* Bytes of workspace ems_create() needs for `cfg` (0 if cfg is invalid). */
@@ -268,16 +282,22 @@ ems_status transport_events(ems_ctx* ctx, const ems_event_batch* batch, int32_t 
  *     EMS_E_STATE): escaping tracks by species and log-energy bin of the grid;
  *   status (host, n): EMS_OK, EMS_NOT_READY (still in flight) or EMS_E_ARG
  *     (unknown id, or an id repeated in this call: only its first entry is read).
- * Rows whose status is not EMS_OK are left untouched.  A read event's slot is
- * released.  Returns EMS_OK if every id was read, EMS_NOT_READY otherwise;
- * EMS_E_HIP releases nothing. */
+ * Rows whose status is not EMS_OK are zero.  A read event's slot is released.
+ * The ids are looked up on the device, in chunks of max_events.  Returns EMS_OK if
+ * every id was read, EMS_NOT_READY otherwise; EMS_E_HIP releases nothing of the
+ * chunk it happened in. */
 ems_status tally_read(ems_ctx* ctx, uint32_t n, const uint32_t* event_ids, double* dep,
                       double* ledger, uint64_t* steps, uint64_t* esc_hist, int32_t* status,
                       void* stream);
 
-/* Run-level counters: steps (host, 3) track-steps by species, esc_hist (host,
- * 3 x 200 or NULL) escaping tracks by species and log-energy bin of the grid. */
-ems_status ems_run_counters(ems_ctx* ctx, uint64_t* steps, uint64_t* esc_hist, void* stream);
+/* Run-level counters since init_geometry: steps (host, 3) track-steps by species,
+ * esc_hist (host, 3 x 200 or NULL) escaping tracks by species and log-energy bin of
+ * the grid, life_hist (host, 3 x 17 or NULL) tracks ended by species and steps taken
+ * (bin 0: none, bin b: 2^(b-1) .. 2^b - 1 steps, bin 16: 32768 or more) -- the
+ * steps-per-track distribution the paper compares between codes (Sec. 3.2,
+ * "Preliminary results"). */
+ems_status ems_run_counters(ems_ctx* ctx, uint64_t* steps, uint64_t* esc_hist, uint64_t* life_hist,
+                            void* stream);
 
 /* The iterations recorded since creation or the last reset (the first 2^20 of them;
  * iterations with an empty pool are not recorded): *n = how many; the first

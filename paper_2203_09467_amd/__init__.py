@@ -51,7 +51,8 @@ class Config(C.Structure):
     _fields_ = [("pool_capacity", C.c_uint32), ("max_events", C.c_uint32),
                 ("max_bins", C.c_uint32), ("queue_capacity", C.c_uint32), ("seed", C.c_uint32),
                 ("precision", C.c_int), ("energy_budget", C.c_double), ("flags", C.c_uint32),
-                ("iterations_per_sync", C.c_uint32), ("spill_capacity", C.c_uint32)]
+                ("iterations_per_sync", C.c_uint32), ("spill_capacity", C.c_uint32),
+                ("field_substeps", C.c_uint32)]
 
 
 class KernelStats(C.Structure):
@@ -70,7 +71,7 @@ class PhysicsOptions(C.Structure):
                 ("ionisation", C.c_int32), ("brems", C.c_int32), ("annihilation", C.c_int32),
                 ("charged_local", C.c_int32), ("continuous_loss", C.c_int32),
                 ("step_alpha", C.c_double), ("step_rfinal", C.c_double),
-                ("max_steps", C.c_uint32)]
+                ("max_steps", C.c_uint32), ("msc", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -116,7 +117,7 @@ class StepRecord(C.Structure):
 
 SOA_FIELDS = [("x", "f8"), ("y", "f8"), ("z", "f8"), ("u", "f8"), ("v", "f8"), ("w", "f8"),
               ("T", "f8"), ("nlam", "f8"), ("k0", "u4"), ("k1", "u4"), ("k2", "u4"),
-              ("event", "u4"), ("nstep", "u4"), ("species", "i4"), ("vol", "i4")]
+              ("event", "u4"), ("nstep", "u4"), ("species", "i4"), ("vol", "i4"), ("vcap", "u4")]
 
 
 class TrackSoA(C.Structure):
@@ -144,7 +145,8 @@ _sigs = {
     "tally_read": (C.c_int, [C.c_void_p, C.c_uint32, _P(C.c_uint32), _P(C.c_double),
                              _P(C.c_double), _P(C.c_uint64), _P(C.c_uint64), _P(C.c_int32),
                              C.c_void_p]),
-    "ems_run_counters": (C.c_int, [C.c_void_p, _P(C.c_uint64), _P(C.c_uint64), C.c_void_p]),
+    "ems_run_counters": (C.c_int, [C.c_void_p, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64),
+                                   C.c_void_p]),
     "ems_step_stats": (C.c_int, [C.c_void_p, _P(KernelStats), C.c_int32]),
     "ems_iteration_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, _P(C.c_uint64), C.c_int32]),
     "ems_step_once": (C.c_int, [C.c_void_p, _P(TrackSoA), C.c_uint32, C.c_void_p, _P(TrackSoA),
@@ -260,12 +262,17 @@ def tally_read(ctx, event_ids, n_bins: int, stream=None, steps: bool = False,
     return out
 
 
-def run_counters(ctx, stream=None):
+LIFE_BINS = 17
+
+
+def run_counters(ctx, stream=None, life=False):
+    """(steps by species, escape histogram 3 x 200[, steps-per-track histogram 3 x 17])."""
     steps = np.zeros(3, np.uint64)
     hist = np.zeros((3, NGRID), np.uint64)
+    lh = np.zeros((3, LIFE_BINS), np.uint64)
     _check(_lib.ems_run_counters(ctx, _np_ptr(steps, C.c_uint64), _np_ptr(hist, C.c_uint64),
-                                 _stream(stream)), "ems_run_counters")
-    return steps, hist
+                                 _np_ptr(lh, C.c_uint64), _stream(stream)), "ems_run_counters")
+    return (steps, hist, lh) if life else (steps, hist)
 
 
 # --------------------------------------------------------------------------- torch-side helpers
@@ -324,11 +331,11 @@ class Context:
     def __init__(self, pool_capacity=1 << 20, max_events=1024, max_bins=128,
                  queue_capacity=1 << 20, seed=1, precision=EMS_FP64, energy_budget=0.0,
                  time_steps=False, iterations_per_sync=0, event_escape=False, spill_capacity=0,
-                 device="cuda"):
+                 field_substeps=0, device="cuda"):
         import torch
         flags = (EMS_FLAG_TIME_STEPS if time_steps else 0) | (EMS_FLAG_EVENT_ESCAPE if event_escape else 0)
         self.cfg = Config(pool_capacity, max_events, max_bins, queue_capacity, seed, precision,
-                          energy_budget, flags, iterations_per_sync, spill_capacity)
+                          energy_budget, flags, iterations_per_sync, spill_capacity, field_substeps)
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise EmsError(-1, "ems_workspace_bytes")
@@ -360,8 +367,8 @@ class Context:
     def read(self, event_ids, stream=None, steps=False, escape=False):
         return tally_read(self.h, event_ids, self.n_bins, stream, steps, escape)
 
-    def counters(self, stream=None):
-        return run_counters(self.h, stream)
+    def counters(self, stream=None, life=False):
+        return run_counters(self.h, stream, life)
 
     def iteration_log(self, reset=False) -> np.ndarray:
         """Per-iteration records (numpy structured array, ITERATION_DTYPE)."""
@@ -379,7 +386,8 @@ class Context:
 
     def step_once(self, states: dict, stream=None):
         """Step the given states (dict of numpy arrays: species, energy, vol, pos, dir, nlam,
-        key, nstep, event) once; returns (records, outputs dict of numpy arrays)."""
+        key, nstep, event, optionally vcap) once; returns (records, outputs dict of numpy
+        arrays)."""
         import torch
         n = len(states["species"])
         cols = {
@@ -388,6 +396,7 @@ class Context:
             "T": states["energy"], "nlam": states["nlam"], "k0": states["key"][:, 0],
             "k1": states["key"][:, 1], "k2": states["key"][:, 2], "event": states["event"],
             "nstep": states["nstep"], "species": states["species"], "vol": states["vol"],
+            "vcap": states.get("vcap", np.zeros(n, np.uint32)),
         }
         dev_in = {}
         for k, dt in SOA_FIELDS:

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ems_slotmap.h"
+
 namespace ems {
 
 constexpr int kGrid = 200;            // nodes of the log energy grid, 1 keV .. 100 GeV
@@ -22,15 +24,22 @@ constexpr int kLedgerSteps = 4;       // first of the three track-step words
 // doubles per event row gathered for tally_read after the deposits: E_in, escaped,
 // killed, pairs, annihilations, track-steps of photons, electrons, positrons
 constexpr uint32_t kRowLedger = 8;
-constexpr uint32_t kVolOut = 0x3FFFFFFu;  // meta volume of a primary that starts outside
+constexpr int kLifeBins = 17;  // steps per track: 0, 1, 2-3, 4-7, ..., >= 32768
+constexpr uint32_t kVolOut = 0xFFFFFu;  // meta volume of a primary that starts outside
+constexpr uint32_t kVolMask = 0xFFFFFu;  // meta bits 6-25: volume
+constexpr int kVcapShift = 26;           // meta bits 26-31: capped vacuum field steps in a row
+// meta bit 3 with bit 2 (put-off interaction) clear: a curved move suspended
+// between launches (with bit 2 set, bits 3-5 name the interaction's queue)
+constexpr uint32_t kMidMove = 8u;
 constexpr uint32_t kRestStep = 0xFFFFFFFFu;
 constexpr int kMaxTrial = 1000;
 constexpr int kBlock = 256;
 constexpr uint32_t kStageMaxBytes = 64u * 1024u;  // per-block LDS budget of the staged run data
 
 // Tracks in flight, SoA.  meta = species (bits 0-1) | pending (bit 2) | queue of
-// the pending interaction (bits 3-5) | volume << 6; a pending track ended its last
-// step in an interaction that was put off for lack of output room.  Photons and
+// the pending interaction (bits 3-5) | volume (bits 6-25) | field steps in vacuum
+// that ended on their substep cap, in a row (bits 26-31); a pending track ended its
+// last step in an interaction that was put off for lack of output room.  Photons and
 // charged tracks live in separate pools so that a wavefront steps one species
 // class, each double-buffered.  A Pool passed to the step kernels is the set of
 // all four buffers: for every field, buffer (class c, parity b) occupies elements
@@ -39,6 +48,11 @@ constexpr uint32_t kStageMaxBytes = 64u * 1024u;  // per-block LDS budget of the
 struct Pool {
   double *x, *y, *z, *u, *v, *w, *T, *nlam;
   uint32_t *k0, *k1, *k2, *evt, *nstep, *meta, *src;
+  // state of a curved move suspended between launches (read and written only for
+  // tracks whose meta word carries kMidMove): substeps done, next trial length,
+  // path travelled
+  uint32_t* fsub;
+  double *fh, *ftrav;
 };
 
 // Tracks that ended their step in a discrete interaction (or a positron that
@@ -84,15 +98,23 @@ enum StatWord {
   kSQueued = 7,    // tracks queued for an interaction
   kSStall = 8,     // iterations in which no interaction could be done for lack of room
   kSBusy = 9,      // iterations with a non-empty pool
-  kSPeak = 10      // largest pool
+  kSPeak = 10,     // largest pool
+  kSEnergy = 11    // kinetic energy (keV) of the tracks written to the output pools this
+                   // iteration: cleared at every iteration, so after the interval it is
+                   // the pool's (summed over the copies)
 };
 constexpr int kLineWords = 32;  // 64-bit words per line
+// the steps-per-track histogram is kept in kStatCopies copies kLifeStride words apart
+// (a block adds to copy blockIdx % kStatCopies): its few bins take an update from
+// nearly every block
+constexpr int kLifeStride = 64;
 
 struct MatParams {
   double Tc, kc;      // production thresholds (delta rays, brems photons)
   double Rtrk[3];     // range table at the tracking cut, per species
+  double X0;          // radiation length, cm
   float Rtrk_f[3];
-  float Tc_f, kc_f;
+  float Tc_f, kc_f, X0_f;
   int vacuum;
 };
 
@@ -107,7 +129,8 @@ struct Params {
   double tcut, alpha, rfinal;
   float tcut_f, alpha_f, rfinal_f;
   uint32_t max_steps;
-  int charged_local, cont_loss;
+  uint32_t sub_per_step;  // curved-move substeps per track-step of a launch before suspension
+  int charged_local, cont_loss, msc;
   int gkind, nvol, nbins;
   uint32_t max_events;
   const double* bounds;
@@ -117,8 +140,9 @@ struct Params {
   // quadric-surface cells (gkind == EMS_GEOM_CSG): surface coefficients (10 each),
   // the faces of each cell (surface * 2 + side), and per face code the cells that
   // have it, in increasing order (the candidates entered through that face)
-  int n_surf;
+  int n_surf, n_faces;
   const double* surf;
+  const unsigned char* plane;  // 1 if surface s has no quadratic term
   const int* face_off;
   const int* faces;
   const int* cand_off;
@@ -129,10 +153,37 @@ struct Params {
   unsigned long long* ledger;    // [slot][kLedger]
   int* alive;                    // [slot] tracks alive or queued
   const double* scale;           // [slot] fixed-point scale 2^s
-  uint32_t* done;                // [slot] list of finished slots (append)
+  uint32_t* slot_state;          // [slot] 0 free, 1 in flight, 2 finished, 3 being read
   unsigned long long* ctr;       // kNumLines x kLineWords iteration counters
   unsigned long long* esc_hist;  // [3][kGrid] escaping tracks of the run
   unsigned long long* ev_esc;    // [slot][3][kGrid] escaping tracks per event, or null
+  unsigned long long* life_hist; // [kStatCopies][kLifeStride]: [3][kLifeBins] tracks ended,
+                                 // by species and steps taken
+};
+
+// Event slots and ids, kept on the device so that submitting and reading a batch
+// costs the host nothing per event.  free: stack of free slots (its height is
+// mirrored by the host); map: open-addressing id -> slot table (power-of-two size,
+// linear probing) of entries (slot + 1) << 32 | id, 0 = empty, kMapTomb = erased;
+// id: the id of each slot; claim: during a read, the first position in the call
+// naming the slot.
+struct EvSlots {
+  uint32_t* free;
+  unsigned long long* map;
+  uint32_t mask;
+  uint32_t* state;
+  uint32_t* id;
+  uint32_t* claim;
+  uint32_t* counter;  // pushes onto the free stack during a read
+  uint32_t n;         // slots
+};
+// bits of the batch check word set by the submission kernels
+enum BatchFlag : unsigned long long {
+  kBadSpecies = 1, kBadEnergy = 2, kBadPos = 4, kBadDir = 8,
+  kBadEmpty = 16,     // an event without primaries
+  kBadLarge = 32,     // an event with more primaries than a quarter of the pool
+  kBadDup = 64,       // an id already unread, or twice in the batch
+  kBadMap = 128       // the id table is full (cannot happen while it is rebuilt in time)
 };
 
 // Pending primaries (ring of queue_capacity entries).

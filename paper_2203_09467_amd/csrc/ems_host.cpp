@@ -23,6 +23,7 @@
 
 #include "emshower.h"
 #include "ems_device.h"
+#include "ems_batches.h"
 #include "ems_host.h"
 
 using namespace ems;
@@ -45,6 +46,8 @@ ems_status fail(ems_status s, const std::string& msg) {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxPerSync = 32;
+// curved-move substeps per track-step of a launch (field_substeps = 0)
+constexpr uint32_t kSubPerStep = 4;
 constexpr uint32_t kMaxVol = 4096;
 constexpr uint32_t kMaxSurf = 4096;
 constexpr uint32_t kMaxFaces = 32768;
@@ -60,66 +63,6 @@ struct Carver {
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off = align_up(off + n * sizeof(T));
     return p;
-  }
-};
-
-struct EventInfo {
-  uint32_t slot;
-  uint32_t n_prim, n_gamma;  // primaries, of which photons
-  double e_in;
-};
-
-// Event id -> slot of the unread events: open addressing with linear probing over a
-// power-of-two table holding slot + 1 (0 = empty); the id of a slot is looked up in
-// the context's slot_id.  Erasing shifts the entries of the probe run back, so the
-// table needs no tombstones.
-struct IdMap {
-  std::vector<uint32_t> t;
-  uint32_t mask = 0;
-  void init(uint32_t max_events) {
-    uint32_t c = 16;
-    while (c < 2u * max_events) c <<= 1;
-    t.assign(c, 0u);
-    mask = c - 1;
-  }
-  void clear() { std::fill(t.begin(), t.end(), 0u); }
-  uint32_t home(uint32_t id) const {
-    return (uint32_t)(((uint64_t)id * 0x9E3779B97F4A7C15ull) >> 32) & mask;
-  }
-  // slot of id, or -1
-  int64_t find(uint32_t id, const std::vector<uint32_t>& slot_id) const {
-    for (uint32_t h = home(id);; h = (h + 1) & mask) {
-      const uint32_t v = t[h];
-      if (v == 0) return -1;
-      if (slot_id[v - 1] == id) return (int64_t)(v - 1);
-    }
-  }
-  // false if id is present already (slot_id[slot] must already hold id)
-  bool insert(uint32_t id, uint32_t slot, const std::vector<uint32_t>& slot_id) {
-    for (uint32_t h = home(id);; h = (h + 1) & mask) {
-      const uint32_t v = t[h];
-      if (v == 0) {
-        t[h] = slot + 1;
-        return true;
-      }
-      if (v - 1 != slot && slot_id[v - 1] == id) return false;
-    }
-  }
-  void erase(uint32_t id, const std::vector<uint32_t>& slot_id) {
-    uint32_t h = home(id);
-    while (t[h] != 0 && slot_id[t[h] - 1] != id) h = (h + 1) & mask;
-    if (t[h] == 0) return;
-    uint32_t hole = h;
-    for (uint32_t j = (h + 1) & mask; t[j] != 0; j = (j + 1) & mask) {
-      const uint32_t k = home(slot_id[t[j] - 1]);
-      // move t[j] into the hole unless its home lies cyclically in (hole, j]
-      const bool stays = hole <= j ? (k > hole && k <= j) : (k > hole || k <= j);
-      if (!stays) {
-        t[hole] = t[j];
-        hole = j;
-      }
-    }
-    t[hole] = 0;
   }
 };
 
@@ -144,31 +87,35 @@ struct ems_ctx {
   int* geo_bin = nullptr;
   double* e_in = nullptr;
   double* scale = nullptr;
+  // staging of one batch (submission) or one chunk of a read, max_events rows
   int64_t* stage_off = nullptr;
-  uint32_t* stage_ng = nullptr;  // photons per event of a submitted batch
+  uint32_t* stage_flag = nullptr;  // per event of a batch: its id was entered
   uint32_t* stage_slot = nullptr;
   uint32_t* stage_id = nullptr;
-  double* stage_out = nullptr;
+  double* stage_e = nullptr;       // per event of a batch: kinetic energy
+  int32_t* stage_status = nullptr;
+  double* stage_dep = nullptr;
+  double* stage_led = nullptr;
+  unsigned long long* stage_steps = nullptr;
   unsigned long long* stage_esc = nullptr;  // per-event escape spectra read back, or null
   unsigned long long* ctr = nullptr;
-  // host mirror of the counters and done list: pinned, or in the vectors below
+  // host mirror of the counters: pinned, or in the vector below
   bool pinned = true;
   std::vector<unsigned long long> h_ctr_buf;
-  std::vector<uint32_t> h_done_buf;
   unsigned long long* h_ctr = nullptr;
   uint64_t run_steps[3] = {0, 0, 0};  // track-steps by species since init_geometry
-  uint32_t* h_done = nullptr;
-  // event slots
-  std::vector<uint32_t> free_slots;
-  std::vector<int> slot_state;  // 0 free, 1 queued or in flight, 2 finished, 3 being read
-  std::vector<uint32_t> slot_id;
-  std::vector<double> slot_e;
-  IdMap id_to_slot;
-  std::deque<EventInfo> pending;
+  // event slots and ids live on the device (EvSlots); the host mirrors the number of
+  // free slots and counts erased id entries (the table is rebuilt past a quarter)
+  EvSlots slots{};
+  uint32_t n_free = 0;
+  uint64_t tombs = 0;
+  bool ev_reset = true;  // the device slot state must be (re)initialised
+  ems::PendingEvents pending;
   uint32_t q_head = 0, q_count = 0;
-  uint64_t pending_prims = 0;
   uint64_t done_unread = 0;  // finished events not yet read
-  double e_flight = 0.0;
+  // kinetic energy of the pool after the last sync interval (measured on the device)
+  // and of the primaries admitted since
+  double e_pool = 0.0, e_adm = 0.0;
   // tracks waiting in pinned host memory: a stack of SoA rows [0, spill_top)
   Pool hs{};
   void* hs_block = nullptr;
@@ -204,6 +151,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   set.nstep = c.take<uint32_t>(4 * N);
   set.meta = c.take<uint32_t>(4 * N);
   set.src = c.take<uint32_t>(4 * N);
+  set.fsub = c.take<uint32_t>(4 * N);
+  set.fh = c.take<double>(4 * N);
+  set.ftrav = c.take<double>(4 * N);
   IQueue iq;
   const size_t NQ = (size_t)kNumQueues * N;
   iq.x = c.take<double>(NQ);
@@ -227,6 +177,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   int* gm = c.take<int>(kMaxVol);
   int* gbin = c.take<int>(kMaxVol);
   double* gsurf = c.take<double>((size_t)kMaxSurf * 10);
+  unsigned char* gplane = c.take<unsigned char>(kMaxSurf);
   int* gfoff = c.take<int>(kMaxVol + 1);
   int* gfaces = c.take<int>(kMaxFaces);
   int* gcoff = c.take<int>(2 * kMaxSurf + 1);
@@ -236,9 +187,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   int* alive = c.take<int>(E);
   double* scale = c.take<double>(E);
   double* e_in = c.take<double>(E);
-  uint32_t* done = c.take<uint32_t>(E);
   unsigned long long* ctr = c.take<unsigned long long>(kNumLines * kLineWords);
   unsigned long long* esc = c.take<unsigned long long>(3 * kGrid);
+  unsigned long long* life = c.take<unsigned long long>(kStatCopies * kLifeStride);
   const bool ev_esc_on = (cfg.flags & EMS_FLAG_EVENT_ESCAPE) != 0;
   unsigned long long* ev_esc = ev_esc_on ? c.take<unsigned long long>(E * 3 * kGrid) : nullptr;
   unsigned long long* stage_esc = ev_esc_on ? c.take<unsigned long long>(E * 3 * kGrid) : nullptr;
@@ -262,7 +213,22 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   uint32_t* sg = c.take<uint32_t>(E);
   uint32_t* ss = c.take<uint32_t>(E);
   uint32_t* si = c.take<uint32_t>(E);
-  double* sout = c.take<double>(E * (B + kRowLedger));
+  double* se = c.take<double>(E);
+  int32_t* sst = c.take<int32_t>(E);
+  double* sdep = c.take<double>(E * B);
+  double* sled = c.take<double>(E * 5);
+  unsigned long long* sstep = c.take<unsigned long long>(E * 3);
+  size_t mcap = 16;
+  while (mcap < 2 * E) mcap <<= 1;
+  EvSlots ev;
+  ev.free = c.take<uint32_t>(E);
+  ev.map = c.take<unsigned long long>(mcap);
+  ev.mask = (uint32_t)(mcap - 1);
+  ev.state = c.take<uint32_t>(E);
+  ev.id = c.take<uint32_t>(E);
+  ev.claim = c.take<uint32_t>(E);
+  ev.counter = c.take<uint32_t>(1);
+  ev.n = (uint32_t)E;
   if (!x) return;
   x->set = set;
   for (int cl = 0; cl < 2; ++cl)
@@ -284,6 +250,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
       p.nstep = set.nstep + o;
       p.meta = set.meta + o;
       p.src = set.src + o;
+      p.fsub = set.fsub + o;
+      p.fh = set.fh + o;
+      p.ftrav = set.ftrav + o;
     }
   x->iq = iq;
   x->tab_d = tab_d;
@@ -297,6 +266,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->P.vmat = gm;
   x->P.vbin = gbin;
   x->P.surf = gsurf;
+  x->P.plane = gplane;
   x->P.face_off = gfoff;
   x->P.faces = gfaces;
   x->P.cand_off = gcoff;
@@ -305,10 +275,12 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->P.ledger = ledger;
   x->P.alive = alive;
   x->P.scale = scale;
-  x->P.done = done;
+  x->P.slot_state = ev.state;
+  x->slots = ev;
   x->P.ctr = ctr;
   x->P.esc_hist = esc;
   x->P.ev_esc = ev_esc;
+  x->P.life_hist = life;
   x->stage_esc = stage_esc;
   x->scale = scale;
   x->e_in = e_in;
@@ -318,10 +290,14 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   x->spill_hist = sh;
   x->spill_cnt = sc;
   x->stage_off = so;
-  x->stage_ng = sg;
+  x->stage_flag = sg;
   x->stage_slot = ss;
   x->stage_id = si;
-  x->stage_out = sout;
+  x->stage_e = se;
+  x->stage_status = sst;
+  x->stage_dep = sdep;
+  x->stage_led = sled;
+  x->stage_steps = sstep;
 }
 
 // Per-event score indices must fit the 28 index bits of the kernels' score keys.
@@ -332,32 +308,30 @@ bool config_ok(const ems_config* c) {
   return c->pool_capacity >= 64 && c->pool_capacity <= (1u << 30) && E >= 1 && E < (1u << 26) &&
          c->max_bins >= 1 && E * c->max_bins < (1ull << 28) &&
          (!ev_esc || E * 3 * kGrid < (1ull << 28)) && c->queue_capacity >= 1 &&
-         c->iterations_per_sync <= kMaxPerSync &&
+         c->iterations_per_sync <= kMaxPerSync && c->field_substeps <= 1024 &&
          (c->flags & ~(EMS_FLAG_TIME_STEPS | EMS_FLAG_EVENT_ESCAPE)) == 0 &&
          (c->precision == EMS_FP64 || c->precision == EMS_MIXED);
 }
 
+// Forget every event: all slots free (the device side is reset by the next call that
+// has a stream, see ensure_events), nothing queued, nothing in flight.
 void reset_events(ems_ctx* x) {
-  const uint32_t E = x->cfg.max_events;
-  x->free_slots.resize(E);
-  for (uint32_t i = 0; i < E; ++i) x->free_slots[i] = E - 1 - i;
-  x->slot_state.assign(E, 0);
-  x->slot_id.assign(E, 0);
-  x->slot_e.assign(E, 0.0);
-  x->id_to_slot.init(E);
+  x->n_free = x->cfg.max_events;
+  x->tombs = 0;
+  x->ev_reset = true;
   x->pending.clear();
   x->q_head = 0;
   x->q_count = 0;
-  x->pending_prims = 0;
   x->done_unread = 0;
-  x->e_flight = 0.0;
+  x->e_pool = x->e_adm = 0.0;
   x->nG = x->nC = 0;
   x->cur = 0;
   x->spill_top = 0;
 }
 
-// Bytes of pinned host memory per spilled track (the SoA state of Pool without src).
-constexpr size_t kHostTrackBytes = 8 * sizeof(double) + 6 * sizeof(uint32_t);
+// Bytes of pinned host memory per spilled track (the SoA state of Pool without src,
+// with the state of a suspended curved move).
+constexpr size_t kHostTrackBytes = 10 * sizeof(double) + 7 * sizeof(uint32_t);
 
 void carve_host(ems_ctx* x, uint64_t cap) {
   char* b = static_cast<char*>(x->hs_block);
@@ -382,6 +356,9 @@ void carve_host(ems_ctx* x, uint64_t cap) {
   h.nstep = reinterpret_cast<uint32_t*>(take(4));
   h.meta = reinterpret_cast<uint32_t*>(take(4));
   h.src = nullptr;
+  h.fsub = reinterpret_cast<uint32_t*>(take(4));
+  h.fh = reinterpret_cast<double*>(take(8));
+  h.ftrav = reinterpret_cast<double*>(take(8));
 }
 
 // Copy n track rows between a device pool view (from row d) and the host stack
@@ -410,6 +387,9 @@ hipError_t copy_rows(const Pool& dev, size_t d, const Pool& host, size_t h, size
   EMS_COPY_FIELD(evt);
   EMS_COPY_FIELD(nstep);
   EMS_COPY_FIELD(meta);
+  EMS_COPY_FIELD(fsub);
+  EMS_COPY_FIELD(fh);
+  EMS_COPY_FIELD(ftrav);
 #undef EMS_COPY_FIELD
   return hipSuccess;
 }
@@ -449,9 +429,6 @@ ems_status create_context(const ems_config* cfg, void* d_workspace, size_t bytes
   if (pinned) {
     hipError_t e = hipHostMalloc((void**)&x->h_ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                                  hipHostMallocDefault);
-    if (e == hipSuccess)
-      e = hipHostMalloc((void**)&x->h_done, (size_t)cfg->max_events * sizeof(uint32_t),
-                        hipHostMallocDefault);
     if (e == hipSuccess && cfg->spill_capacity > 0) {
       e = hipHostMalloc(&x->hs_block, (size_t)cfg->spill_capacity * kHostTrackBytes, hipHostMallocDefault);
       if (e == hipSuccess) carve_host(x, cfg->spill_capacity);
@@ -462,9 +439,7 @@ ems_status create_context(const ems_config* cfg, void* d_workspace, size_t bytes
     }
   } else {
     x->h_ctr_buf.assign((size_t)kNumLines * kLineWords, 0ull);
-    x->h_done_buf.assign(cfg->max_events, 0u);
     x->h_ctr = x->h_ctr_buf.data();
-    x->h_done = x->h_done_buf.data();
   }
   x->per_sync = cfg->iterations_per_sync == 0 ? 8 : (int)cfg->iterations_per_sync;
   if (cfg->flags & EMS_FLAG_TIME_STEPS) {
@@ -500,7 +475,6 @@ void ems_destroy(ems_ctx* x) {
   if (!x) return;
   if (x->pinned) {
     if (x->h_ctr) (void)hipHostFree(x->h_ctr);
-    if (x->h_done) (void)hipHostFree(x->h_done);
     if (x->hs_block) (void)hipHostFree(x->hs_block);
   }
   for (hipEvent_t e : x->ev)
@@ -542,8 +516,10 @@ ems_status init_physics_tables(ems_ctx* x, const ems_material* mats, int32_t n_m
   P.alpha_f = (float)P.alpha;
   P.rfinal_f = (float)P.rfinal;
   P.max_steps = o->max_steps;
+  P.sub_per_step = x->cfg.field_substeps == 0 ? kSubPerStep : x->cfg.field_substeps;
   P.charged_local = o->charged_local != 0;
   P.cont_loss = o->continuous_loss != 0;
+  P.msc = o->msc != 0;
   x->opts = *o;
   x->tables = true;
   x->geometry = false;
@@ -604,6 +580,12 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
     std::vector<double> zeros(g->n_vol + 1, 0.0);
     HIP_OK(hipMemcpyAsync(x->geo_bounds, zeros.data(), sizeof(double) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)x->P.surf, g->surfaces, sizeof(double) * 10 * g->n_surf, hipMemcpyHostToDevice, s));
+    std::vector<unsigned char> plane(g->n_surf);
+    for (int k = 0; k < g->n_surf; ++k) {
+      const double* q = g->surfaces + 10 * k;
+      plane[k] = q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0 && q[3] == 0.0 && q[4] == 0.0 && q[5] == 0.0;
+    }
+    HIP_OK(hipMemcpyAsync((void*)x->P.plane, plane.data(), g->n_surf, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)x->P.face_off, g->face_off, sizeof(int) * (g->n_vol + 1), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)x->P.faces, g->faces, sizeof(int) * (nf > 0 ? nf : 0), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)x->P.cand_off, cand_off.data(), sizeof(int) * cand_off.size(), hipMemcpyHostToDevice, s));
@@ -624,9 +606,11 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
   P.bz = g->bz;
   P.ftol = g->field_tol;
   P.n_surf = csg ? g->n_surf : 0;
+  P.n_faces = csg ? g->face_off[g->n_vol] : 0;
   HIP_OK(launch_zero_u64(x->ctr, kNumLines * kLineWords, s));
   x->run_steps[0] = x->run_steps[1] = x->run_steps[2] = 0;
   HIP_OK(launch_zero_u64(P.esc_hist, 3 * kGrid, s));
+  HIP_OK(launch_zero_u64(P.life_hist, kStatCopies * kLifeStride, s));
   HIP_OK(hipStreamSynchronize(s));
   reset_events(x);
   x->geometry = true;
@@ -640,110 +624,109 @@ namespace {
 // Submit a batch: slots, ring copy, slot initialisation.  Nothing changes on error.
 // The host work per event is a few array updates and one hash insert; per-event
 // sums (energy, photons) are made on the device.
+// The device slot state after creation or a reset.
+ems_status ensure_events(ems_ctx* x, hipStream_t s) {
+  if (!x->ev_reset) return EMS_OK;
+  HIP_OK(launch_events_reset(x->slots, s));
+  x->ev_reset = false;
+  return EMS_OK;
+}
+
+// Erased id entries slow every probe: past a quarter of the table it is rebuilt.
+ems_status maybe_rebuild(ems_ctx* x, hipStream_t s) {
+  if (x->tombs * 4 <= (uint64_t)x->slots.mask + 1u) return EMS_OK;
+  HIP_OK(launch_map_rebuild(x->slots, s));
+  x->tombs = 0;
+  return EMS_OK;
+}
+
+// Submit a batch: slots, ids and checks on the device (kernels over the batch's
+// events and primaries), one synchronisation; the host keeps the batch's offsets
+// (and, with an energy budget, its events' energies) for admission.
 ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   const uint32_t ne = b->n_events;
   if (ne == 0) return EMS_OK;
   if (!b->event_ids || !b->offsets) return fail(EMS_E_ARG, "transport_events: null ids/offsets");
   if (b->offsets[0] != 0) return fail(EMS_E_ARG, "transport_events: offsets[0] must be 0");
-  const int64_t quarter = (int64_t)(x->cfg.pool_capacity / 4);
-  for (uint32_t e = 0; e < ne; ++e) {
-    const int64_t k = b->offsets[e + 1] - b->offsets[e];
-    if (k < 1) return fail(EMS_E_ARG, "transport_events: every event needs at least one primary");
-    if (k > quarter) return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
-  }
+  if (b->offsets[ne] < (int64_t)ne)
+    return fail(EMS_E_ARG, "transport_events: every event needs at least one primary");
   const uint64_t n = (uint64_t)b->offsets[ne];
   if (!b->species || !b->energy || !b->pos || !b->dir)
     return fail(EMS_E_ARG, "transport_events: null primary arrays");
-  if (ne > x->free_slots.size())
-    return fail(EMS_E_CAPACITY, "transport_events: not enough free event slots");
+  if (ne > x->n_free) return fail(EMS_E_CAPACITY, "transport_events: not enough free event slots");
   if (n + x->q_count > x->cfg.queue_capacity)
     return fail(EMS_E_CAPACITY, "transport_events: primaries exceed the queue capacity");
-  const size_t nf = x->free_slots.size();
-  const uint32_t* slots = x->free_slots.data() + (nf - ne);  // taken from the back
-  // ids: insert; a repeat (unread or within the batch) undoes the inserts
-  auto undo = [&](uint32_t upto) {
-    for (uint32_t e = 0; e < upto; ++e) x->id_to_slot.erase(b->event_ids[e], x->slot_id);
-  };
-  for (uint32_t e = 0; e < ne; ++e) {
-    const uint32_t sl = slots[e];
-    x->slot_id[sl] = b->event_ids[e];
-    if (!x->id_to_slot.insert(b->event_ids[e], sl, x->slot_id)) {
-      undo(e);
-      return fail(EMS_E_ARG, "transport_events: duplicate event id");
-    }
+  {
+    const ems_status st = ensure_events(x, s);
+    if (st != EMS_OK) return st;
   }
   const uint32_t tail = (x->q_head + x->q_count) % x->q.capacity;
-  // validity flags of the batch's primaries: a word of the done line, unused otherwise
+  const bool by_energy = x->cfg.energy_budget > 0.0;
+  // check word of the batch: a word of the done line, unused otherwise
   unsigned long long* bad = x->ctr + kLDone * kLineWords + 1;
-  std::vector<double> ev_e(ne);
-  std::vector<uint32_t> ev_g(ne);
+  std::vector<double> ev_e(by_energy ? ne : 0);
   unsigned long long badw = 0;
   hipError_t e = hipMemcpyAsync(x->stage_off, b->offsets, sizeof(int64_t) * (ne + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(x->stage_slot, slots, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_zero_u64(bad, 1, s);
+  if (e == hipSuccess)
+    e = launch_slots_take(x->slots, x->n_free, x->stage_id, ne, x->stage_slot, x->stage_flag, bad, s);
   if (e == hipSuccess)
     e = launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species, b->energy,
                        b->pos, b->dir, (uint32_t)n, bad, s);
   if (e == hipSuccess)
-    e = launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, x->e_in,
-                          x->scale, x->stage_out, x->stage_ng, s);
-  // primary energy (admission energy budget) and photons (pool sizes) per event
-  if (e == hipSuccess) e = hipMemcpyAsync(ev_e.data(), x->stage_out, ne * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(ev_g.data(), x->stage_ng, ne * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    e = launch_event_init(x->P, x->stage_off, x->stage_slot, b->energy, b->species, ne, (int64_t)n,
+                          x->e_in, x->scale, x->stage_e, (int64_t)(x->cfg.pool_capacity / 4), bad, s);
+  if (e == hipSuccess && by_energy)
+    e = hipMemcpyAsync(ev_e.data(), x->stage_e, ne * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&badw, bad, sizeof(badw), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    undo(ne);
+  if (e != hipSuccess) {  // the device state of the batch is unknown: start over
+    reset_events(x);
     return fail(EMS_E_HIP, std::string("transport_events: ") + hipGetErrorString(e));
   }
-  if (badw) {
-    undo(ne);
+  if (badw) {  // nothing is submitted: the entries made are erased, the slots stay free
+    e = launch_slots_undo(x->slots, x->stage_id, x->stage_slot, x->stage_flag, ne, s);
+    x->tombs += ne;
+    if (e == hipSuccess && maybe_rebuild(x, s) != EMS_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      reset_events(x);
+      return fail(EMS_E_HIP, std::string("transport_events: ") + hipGetErrorString(e));
+    }
+    if (badw & kBadEmpty)
+      return fail(EMS_E_ARG, "transport_events: offsets must increase (every event needs a primary)");
+    if (badw & kBadLarge)
+      return fail(EMS_E_CAPACITY, "transport_events: event larger than a quarter of the pool");
+    if (badw & kBadDup) return fail(EMS_E_ARG, "transport_events: duplicate event id");
+    if (badw & kBadMap) return fail(EMS_E_INTERNAL, "transport_events: event id table full");
     std::string m = "transport_events: invalid primaries:";
-    if (badw & 1ull) m += " species not 0, 1 or 2;";
-    if (badw & 2ull) m += " kinetic energy not in (0, 1e5] MeV;";
-    if (badw & 4ull) m += " position not finite;";
-    if (badw & 8ull) m += " direction not a unit vector;";
+    if (badw & kBadSpecies) m += " species not 0, 1 or 2;";
+    if (badw & kBadEnergy) m += " kinetic energy not in (0, 1e5] MeV;";
+    if (badw & kBadPos) m += " position not finite;";
+    if (badw & kBadDir) m += " direction not a unit vector;";
     return fail(EMS_E_ARG, m);
   }
-  for (uint32_t j = 0; j < ne; ++j) {
-    const uint32_t sl = slots[j];
-    x->slot_state[sl] = 1;
-    x->slot_e[sl] = ev_e[j];
-    x->pending.push_back({sl, (uint32_t)(b->offsets[j + 1] - b->offsets[j]), ev_g[j], ev_e[j]});
-  }
-  x->free_slots.resize(nf - ne);
+  x->pending.push(b->offsets, ne, by_energy ? ev_e.data() : nullptr);
+  x->n_free -= ne;
   x->q_count += (uint32_t)n;
-  x->pending_prims += n;
   return EMS_OK;
 }
 
-// Admit queued events (whole) into the current pools.  The admission kernel runs
-// after k_iter_begin has set the admission cursors to the pool sizes.
+// Admit queued events while the pool has room for their primaries (a quarter of
+// its capacity, for the showers to grow) and the energy budget allows; returns the
+// number of primaries appended to the pools.
 ems_status admit(ems_ctx* x, hipStream_t s, uint32_t* m_out) {
-  uint32_t m = 0, mg = 0;
-  const uint32_t room = x->cfg.pool_capacity / 4;  // keep room for the showers to grow
-  const double budget = x->cfg.energy_budget;
-  const uint32_t n_active = x->nG + x->nC;
-  while (!x->pending.empty()) {
-    const EventInfo& ev = x->pending.front();
-    // an empty pool always takes the next event, so admission cannot stall
-    const bool first = n_active + m == 0;
-    if (!first && n_active + m + ev.n_prim > room) break;
-    if (!first && budget > 0.0 && x->e_flight > 0.0 && x->e_flight + ev.e_in > budget) break;
-    m += ev.n_prim;
-    mg += ev.n_gamma;
-    x->e_flight += ev.e_in;
-    x->pending.pop_front();
-  }
+  const uint64_t room = x->cfg.pool_capacity / 4;
+  const Admitted a = x->pending.admit((uint64_t)x->nG + x->nC, room, x->e_pool + x->e_adm,
+                                      x->cfg.energy_budget);
+  const uint32_t m = (uint32_t)a.prims;
   *m_out = m;
   if (m == 0) return EMS_OK;
+  x->e_adm += a.energy;
   HIP_OK(launch_admit(x->P, x->q, x->set, x->cfg.pool_capacity, x->cur, x->q_head, m, s));
   x->q_head = (x->q_head + m) % x->q.capacity;
   x->q_count -= m;
-  x->pending_prims -= m;
-  x->nG += mg;
-  x->nC += m - mg;
   return EMS_OK;
 }
 
@@ -766,7 +749,6 @@ constexpr uint32_t kStepsPerLaunch = 4;
 // takes more steps per track (the tail of a run, long-lived loopers)
 constexpr uint64_t kTailTracks = 16384;
 constexpr uint32_t kTailStepsPerLaunch = 32;
-constexpr uint32_t kDonePrefetch = 4096;  // finished-event entries read with the counters
 constexpr size_t kLogCap = size_t(1) << 20;  // iteration records kept
 
 // Bring back tracks waiting in host memory once the pool has drained below a quarter
@@ -828,22 +810,24 @@ ems_status spill(ems_ctx* x, hipStream_t s, uint64_t want, uint64_t* moved) {
 ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int iters,
                         bool admit_first, bool full_room, IntervalOut* io) {
   HIP_OK(launch_iter_begin(x->ctr, true, x->nG, x->nC, 0, nullptr, s));
+  // primaries admitted now join the pools at the device's admission cursors (the
+  // split into photons and charged tracks is read back after the interval)
+  uint32_t m = 0;
   if (admit_first && x->spill_top > 0) {
     const ems_status st = unspill(x, s);
     if (st != EMS_OK) return st;
   } else if (admit_first) {
-    uint32_t m = 0;
     const ems_status st = admit(x, s, &m);
     if (st != EMS_OK) return st;
   }
-  if (x->nG + x->nC == 0) {
+  const uint64_t n0 = (uint64_t)x->nG + x->nC + m;
+  if (n0 == 0) {
     if (admit_first && !x->pending.empty())
       return fail(EMS_E_INTERNAL, "transport_events: queued events could not be admitted");
     return EMS_OK;
   }
   const uint32_t cap = x->cfg.pool_capacity;
   const bool mixed = x->cfg.precision == EMS_MIXED;
-  const uint64_t n0 = (uint64_t)x->nG + x->nC;
   const uint32_t bound =
       full_room ? cap : (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(n0, 2 * n0 + kBoundMargin));
   const uint32_t msteps = full_room ? 1u : (n0 < kTailTracks ? kTailStepsPerLaunch : kStepsPerLaunch);
@@ -854,10 +838,8 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
     x->cur = 1 - x->cur;
   }
-  const uint32_t pre = std::min<uint32_t>(x->cfg.max_events, kDonePrefetch);
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, pre * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   uint32_t ilog[4 * kMaxPerSync];
   if (iters > 1)
     HIP_OK(hipMemcpyAsync(ilog, x->iter_log, 4 * (iters - 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -869,7 +851,7 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
   S[kSPeak] = L[kLStats * kLineWords + kSPeak];
   const unsigned long long out = L[kLOut * kLineWords] + L[kLOutI * kLineWords];
   const uint32_t outG = (uint32_t)(out & 0xFFFFFFFFull), outC = (uint32_t)(out >> 32);
-  const uint32_t n_done = std::min((uint32_t)L[kLDone * kLineWords], x->cfg.max_events);
+  const uint32_t n_done = (uint32_t)(L[kLDone * kLineWords] & 0xFFFFFFFFull);  // events finished
   uint64_t queued_last = 0;
   for (int l = 0; l < 4; ++l) {
     const unsigned long long v = L[(kLQueue + l) * kLineWords];
@@ -905,29 +887,19 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
         r.tracks_out = outG + outC;
       }
       if (r.photons + r.charged == 0) continue;
-      r.waiting_primaries = x->pending_prims;
+      r.waiting_primaries = x->pending.prims();
       r.spilled = x->spill_top;
       r.ms = it_ms[j];
       x->log.push_back(r);
     }
   }
-  if (n_done) {
-    if (n_done > pre) {
-      HIP_OK(hipMemcpyAsync(x->h_done, x->P.done, n_done * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
-    }
-    for (uint32_t j = 0; j < n_done; ++j) {
-      const uint32_t sl = x->h_done[j];
-      if (sl < x->slot_state.size() && x->slot_state[sl] == 1) {
-        x->slot_state[sl] = 2;
-        x->done_unread += 1;
-        x->e_flight -= x->slot_e[sl];
-      }
-    }
-    if (x->e_flight < 0.0) x->e_flight = 0.0;
-  }
+  x->done_unread += n_done;
   x->nG = outG;
   x->nC = outC;
+  unsigned long long e_kev = 0;
+  for (int c = 0; c < kStatCopies; ++c) e_kev += L[(kLStats + c) * kLineWords + kSEnergy];
+  x->e_pool = 1e-3 * (double)e_kev;
+  x->e_adm = 0.0;
   io->stepped += S[kSStepG] + S[kSStepC];
   io->deferred += S[kSDeferred];
   io->busy += S[kSBusy];
@@ -945,6 +917,10 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
   if (!x) return fail(EMS_E_ARG, "transport_events: null context");
   if (!x->tables || !x->geometry) return fail(EMS_E_STATE, "transport_events: initialise tables and geometry first");
   hipStream_t s = (hipStream_t)stream;
+  {
+    const ems_status st = ensure_events(x, s);
+    if (st != EMS_OK) return st;
+  }
   if (b) {
     const ems_status st = submit(x, b, s);
     if (st != EMS_OK) return st;
@@ -977,8 +953,8 @@ ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_it
   const uint64_t stepped = io.stepped, deferred = io.deferred, peak = io.peak;
   if (progress) {
     progress->alive = (uint64_t)x->nG + x->nC;
-    progress->queued_primaries = x->pending_prims;
-    progress->queued_events = x->pending.size();
+    progress->queued_primaries = x->pending.prims();
+    progress->queued_events = x->pending.events();
     progress->iterations = io.busy;
     progress->track_steps = stepped;
     progress->deferred = deferred;
@@ -997,86 +973,82 @@ ems_status tally_read(ems_ctx* x, uint32_t n, const uint32_t* ids, double* dep, 
   if (esc_hist && !x->P.ev_esc)
     return fail(EMS_E_STATE, "tally_read: per-event escape spectra need EMS_FLAG_EVENT_ESCAPE");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<uint32_t> slots;
-  std::vector<uint32_t> rows;
-  bool all = true;
-  for (uint32_t j = 0; j < n; ++j) {
-    const int64_t f = x->id_to_slot.find(ids[j], x->slot_id);
-    const uint32_t sl = (uint32_t)f;
-    if (f < 0) {
-      status[j] = EMS_E_ARG;
-      all = false;
-    } else if (x->slot_state[sl] == 3) {  // already read earlier in this call
-      status[j] = EMS_E_ARG;
-      all = false;
-    } else if (x->slot_state[sl] != 2) {
-      status[j] = EMS_NOT_READY;
-      all = false;
-    } else {
-      status[j] = EMS_OK;
-      x->slot_state[sl] = 3;
-      slots.push_back(sl);
-      rows.push_back(j);
-    }
+  {
+    const ems_status st = ensure_events(x, s);
+    if (st != EMS_OK) return st;
   }
+  // per chunk of at most max_events ids, on the device: the slot of each id and its
+  // status, the rows of the finished events (zero for the others) copied straight
+  // into the caller's arrays, then the slots released
   const uint32_t nb = (uint32_t)x->P.nbins;
-  const uint32_t w = nb + kRowLedger;
   const uint32_t chunk = x->cfg.max_events;
   const uint32_t ne = 3 * kGrid;
-  std::vector<double> buf;
-  ems_status st = EMS_OK;
-  for (size_t a = 0; a < slots.size() && st == EMS_OK; a += chunk) {
-    const uint32_t m = (uint32_t)std::min<size_t>(chunk, slots.size() - a);
-    hipError_t e = hipMemcpyAsync(x->stage_slot, slots.data() + a, m * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, s);
+  std::vector<unsigned long long> st3(steps ? 0 : (size_t)std::min(n, chunk) * 3);
+  bool all = true;
+  for (uint32_t a = 0; a < n; a += chunk) {
+    const uint32_t m = std::min(chunk, n - a);
+    hipError_t e = hipMemcpyAsync(x->stage_id, ids + a, m * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_read_find(x->slots, x->stage_id, m, x->stage_slot, x->stage_status, s);
     if (e == hipSuccess)
-      e = launch_gather_tallies(x->P, x->stage_slot, m, x->e_in, x->stage_out,
-                                esc_hist ? x->stage_esc : nullptr, s);
-    buf.resize((size_t)m * w);
+      e = launch_gather_tallies(x->P, x->stage_slot, m, x->e_in, x->stage_dep, x->stage_led,
+                                x->stage_steps, esc_hist ? x->stage_esc : nullptr, s);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(buf.data(), x->stage_out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && esc_hist) {
-      std::vector<uint64_t> eb((size_t)m * ne);
-      e = hipMemcpyAsync(eb.data(), x->stage_esc, eb.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      for (uint32_t r = 0; e == hipSuccess && r < m; ++r)
-        std::memcpy(esc_hist + (size_t)rows[a + r] * ne, eb.data() + (size_t)r * ne, ne * sizeof(uint64_t));
-    }
+      e = hipMemcpyAsync(status + a, x->stage_status, m * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dep + (size_t)a * nb, x->stage_dep, (size_t)m * nb * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ledger + (size_t)a * 5, x->stage_led, (size_t)m * 5 * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(steps ? steps + (size_t)a * 3 : (uint64_t*)st3.data(), x->stage_steps,
+                         (size_t)m * 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && esc_hist)
+      e = hipMemcpyAsync(esc_hist + (size_t)a * ne, x->stage_esc, (size_t)m * ne * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      st = fail(EMS_E_HIP, std::string("tally_read: ") + hipGetErrorString(e));
-      break;
+    if (e != hipSuccess) {  // nothing of this chunk is released: every event stays readable
+      (void)launch_read_unclaim(x->slots, x->stage_slot, m, s);
+      (void)hipStreamSynchronize(s);
+      return fail(EMS_E_HIP, std::string("tally_read: ") + hipGetErrorString(e));
     }
-    for (uint32_t r = 0; r < m; ++r) {
-      const uint32_t j = rows[a + r];
-      const double* row = buf.data() + (size_t)r * w;
-      std::memcpy(dep + (size_t)j * nb, row, nb * sizeof(double));
-      std::memcpy(ledger + (size_t)j * 5, row + nb, 5 * sizeof(double));
-      if (steps)
-        for (int k = 0; k < 3; ++k) steps[(size_t)j * 3 + k] = (uint64_t)row[nb + 5 + k];
+    uint32_t k = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+      k += status[a + j] == EMS_OK;
+      all = all && status[a + j] == EMS_OK;
+    }
+    if (k) {
+      HIP_OK(launch_read_release(x->slots, x->stage_id, x->stage_slot, m, x->n_free, s));
+      x->n_free += k;
+      x->done_unread -= k;
+      x->tombs += k;
+      const ems_status st = maybe_rebuild(x, s);
+      if (st != EMS_OK) return st;
     }
   }
-  if (st != EMS_OK) {  // nothing is released: every event stays readable
-    for (uint32_t sl : slots) x->slot_state[sl] = 2;
-    return st;
-  }
-  x->done_unread -= slots.size();
-  for (uint32_t sl : slots) {  // release, once per slot
-    x->id_to_slot.erase(x->slot_id[sl], x->slot_id);
-    x->slot_state[sl] = 0;
-    x->free_slots.push_back(sl);
-  }
+  HIP_OK(hipStreamSynchronize(s));
   return all ? EMS_OK : EMS_NOT_READY;
 }
 
-ems_status ems_run_counters(ems_ctx* x, uint64_t* steps, uint64_t* esc_hist, void* stream) {
+ems_status ems_run_counters(ems_ctx* x, uint64_t* steps, uint64_t* esc_hist, uint64_t* life_hist,
+                            void* stream) {
   if (!x || !steps) return fail(EMS_E_ARG, "ems_run_counters: null argument");
   if (!x->geometry) return fail(EMS_E_STATE, "ems_run_counters: no geometry");
   hipStream_t s = (hipStream_t)stream;
-  if (esc_hist) {
+  if (esc_hist)
     HIP_OK(hipMemcpyAsync(esc_hist, x->P.esc_hist, 3 * kGrid * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+  std::vector<uint64_t> lh;
+  if (life_hist) {
+    lh.resize(kStatCopies * kLifeStride);
+    HIP_OK(hipMemcpyAsync(lh.data(), x->P.life_hist, lh.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   }
+  if (esc_hist || life_hist) HIP_OK(hipStreamSynchronize(s));
+  if (life_hist)
+    for (int b = 0; b < 3 * kLifeBins; ++b) {
+      uint64_t t = 0;
+      for (int c = 0; c < kStatCopies; ++c) t += lh[(size_t)c * kLifeStride + b];
+      life_hist[b] = t;
+    }
   for (int i = 0; i < 3; ++i) steps[i] = x->run_steps[i];
   return EMS_OK;
 }
@@ -1107,6 +1079,10 @@ ems_status ems_step_once(ems_ctx* x, const ems_track_soa* in, uint32_t n, ems_st
   hipStream_t s = (hipStream_t)stream;
   // every slot of this context is reset: step_once discards any events in flight
   reset_events(x);
+  {
+    const ems_status st = ensure_events(x, s);
+    if (st != EMS_OK) return st;
+  }
   HIP_OK(launch_slots_reset(x->P, s));
   HIP_OK(launch_iter_begin(x->ctr, true, 0, 0, 0, nullptr, s));
   HIP_OK(launch_pool_load(x->P, x->set, x->cfg.pool_capacity, *in, n, s));

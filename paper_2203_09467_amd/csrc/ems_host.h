@@ -30,8 +30,20 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
                           const double* T, const double* pos, const double* dir, uint32_t n,
                           unsigned long long* bad, hipStream_t s);
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
-                             const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
-                             double* scale, double* e_row, uint32_t* g_row, hipStream_t s);
+                             const double* T, const int32_t* sp, uint32_t n_events, int64_t n,
+                             double* e_in, double* scale, double* e_row, int64_t quarter,
+                             unsigned long long* bad, hipStream_t s);
+hipError_t launch_slots_take(const EvSlots& M, uint32_t top, const uint32_t* ids, uint32_t n,
+                             uint32_t* slots, uint32_t* flag, unsigned long long* bad, hipStream_t s);
+hipError_t launch_slots_undo(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
+                             const uint32_t* flag, uint32_t n, hipStream_t s);
+hipError_t launch_events_reset(const EvSlots& M, hipStream_t s);
+hipError_t launch_map_rebuild(const EvSlots& M, hipStream_t s);
+hipError_t launch_read_find(const EvSlots& M, const uint32_t* ids, uint32_t n, uint32_t* slots,
+                            int32_t* status, hipStream_t s);
+hipError_t launch_read_unclaim(const EvSlots& M, const uint32_t* slots, uint32_t n, hipStream_t s);
+hipError_t launch_read_release(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
+                               uint32_t n, uint32_t top, hipStream_t s);
 hipError_t launch_slots_reset(const Params& P, hipStream_t s);
 hipError_t launch_spill_hist(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
                              uint32_t nC, unsigned long long* hist, hipStream_t s);
@@ -46,7 +58,7 @@ hipError_t launch_pool_load(const Params& P, const Pool& S, uint32_t N, const em
 hipError_t launch_pool_dump(const Pool& p, const ems_track_soa& dst, uint32_t n, uint32_t off,
                             hipStream_t s);
 hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_t n,
-                                 const double* e_in, double* out, unsigned long long* esc,
-                                 hipStream_t s);
+                                 const double* e_in, double* dep, double* ledger,
+                                 unsigned long long* steps, unsigned long long* esc, hipStream_t s);
 
 }  // namespace ems

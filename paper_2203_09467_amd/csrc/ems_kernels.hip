@@ -94,6 +94,9 @@ __device__ __forceinline__ void child_key(uint32_t seed, uint32_t p0, uint32_t p
 template <class R>
 struct Px;
 
+// Multiple-scattering draws of a step: two words far above the interaction draws.
+constexpr uint32_t kMscDraw = 0x40000000u;
+
 template <>
 struct Px<double> {
   static __device__ __forceinline__ double uni(uint64_t w) {
@@ -111,6 +114,7 @@ struct Px<double> {
   static __device__ __forceinline__ double rtrk(const MatParams& m, int s) { return m.Rtrk[s]; }
   static __device__ __forceinline__ double alpha(const Params& P) { return P.alpha; }
   static __device__ __forceinline__ double rfin(const Params& P) { return P.rfinal; }
+  static __device__ __forceinline__ double x0(const MatParams& m) { return m.X0; }
 };
 
 template <>
@@ -130,6 +134,7 @@ struct Px<float> {
   static __device__ __forceinline__ float rtrk(const MatParams& m, int s) { return m.Rtrk_f[s]; }
   static __device__ __forceinline__ float alpha(const Params& P) { return P.alpha_f; }
   static __device__ __forceinline__ float rfin(const Params& P) { return P.rfinal_f; }
+  static __device__ __forceinline__ float x0(const MatParams& m) { return m.X0_f; }
 };
 
 // ------------------------------------------------------------------ tables
@@ -139,11 +144,27 @@ struct Px<float> {
 // the material parameters.  The step kernels address them either in global memory
 // or in a copy staged in LDS by each block (the tables of the block's species
 // class only, so a staged table starts at species sp0).
+// Geometry read by the navigation: slab planes or shell radii, or the quadric cells'
+// surfaces (with a per-surface plane flag), faces and entry candidates.
+struct Geo {
+  const double* bounds;
+  const double* surf;
+  const unsigned char* plane;
+  const int* face_off;
+  const int* faces;
+  const int* cand_off;
+  const int* cand;
+};
+
+__device__ __forceinline__ Geo global_geo(const Params& P) {
+  return Geo{P.bounds, P.surf, P.plane, P.face_off, P.faces, P.cand_off, P.cand};
+}
+
 template <class R>
 struct View {
   const R* tab;
   int mstride, sp0;  // elements per material, first species held
-  const double* bounds;
+  Geo g;
   const int* vmat;
   const int* vbin;
   const MatParams* mat;
@@ -247,32 +268,43 @@ __device__ __forceinline__ double csg_a(const double* q, double u, double v, dou
   return q[0] * u * u + q[1] * v * v + q[2] * w * w + q[3] * u * v + q[4] * v * w + q[5] * w * u;
 }
 
+// A plane (every quadratic coefficient zero) is evaluated from its linear terms
+// alone: the zero terms add nothing but the sign of a zero, which no decision reads.
+__device__ __forceinline__ double plane_c(const double* q, double x, double y, double z) {
+#pragma clang fp contract(off)
+  return q[6] * x + q[7] * y + q[8] * z + q[9];
+}
+__device__ __forceinline__ double plane_B(const double* q, double u, double v, double w) {
+#pragma clang fp contract(off)
+  return q[6] * u + q[7] * v + q[8] * w;
+}
+
 // Side of surface q at (x,y,z) moving along (u,v,w): sign of f, on the surface the
 // sign of df/dt, on a tangent the sign of a (zero counts as +1).
-__device__ __forceinline__ int csg_side(const double* q, double x, double y, double z, double u,
-                                        double v, double w) {
-  const double c = csg_c(q, x, y, z);
+__device__ __forceinline__ int csg_side(const double* q, bool pl, double x, double y, double z,
+                                        double u, double v, double w) {
+  const double c = pl ? plane_c(q, x, y, z) : csg_c(q, x, y, z);
   if (c > 0.0) return 1;
   if (c < 0.0) return -1;
-  const double B = csg_B(q, x, y, z, u, v, w);
+  const double B = pl ? plane_B(q, u, v, w) : csg_B(q, x, y, z, u, v, w);
   if (B > 0.0) return 1;
   if (B < 0.0) return -1;
-  return csg_a(q, u, v, w) >= 0.0 ? 1 : -1;
+  return (pl ? 0.0 : csg_a(q, u, v, w)) >= 0.0 ? 1 : -1;
 }
 
 // Distance to where f leaves side sg: the root at which df/dt has the sign -sg,
 // written without cancellation; a root behind counts as 0 if the track is moving
 // off side sg right now, else as no crossing.
-__device__ __forceinline__ double csg_exit(const double* q, double x, double y, double z, double u,
-                                           double v, double w, double sg) {
+__device__ __forceinline__ double csg_exit(const double* q, bool pl, double x, double y, double z,
+                                           double u, double v, double w, double sg) {
 #pragma clang fp contract(off)
-  const double a = csg_a(q, u, v, w);
-  const double B = csg_B(q, x, y, z, u, v, w);
-  const double c = csg_c(q, x, y, z);
+  const double a = pl ? 0.0 : csg_a(q, u, v, w);
+  const double B = pl ? plane_B(q, u, v, w) : csg_B(q, x, y, z, u, v, w);
   const double b = 0.5 * B;
+  if (a == 0.0 && !(sg * b < 0.0)) return HUGE_VAL;  // a plane never left this way
+  const double c = pl ? plane_c(q, x, y, z) : csg_c(q, x, y, z);
   double t;
   if (a == 0.0) {
-    if (!(sg * b < 0.0)) return HUGE_VAL;
     t = c / (-2.0 * b);
   } else {
     const double D = b * b - a * c;
@@ -286,67 +318,71 @@ __device__ __forceinline__ double csg_exit(const double* q, double x, double y, 
 
 // Does cell m hold the point moving along (u,v,w)?  Faces on surface `forced` count
 // as satisfied.
-__device__ __forceinline__ bool csg_holds(const Params& P, int m, double x, double y, double z,
+__device__ __forceinline__ bool csg_holds(const Geo& G, int m, double x, double y, double z,
                                           double u, double v, double w, int forced) {
-  for (int j = P.face_off[m]; j < P.face_off[m + 1]; ++j) {
-    const int f = P.faces[j];
-    if ((f >> 1) == forced) continue;
-    if (csg_side(P.surf + 10 * (f >> 1), x, y, z, u, v, w) != ((f & 1) ? 1 : -1)) return false;
+  for (int j = G.face_off[m]; j < G.face_off[m + 1]; ++j) {
+    const int f = G.faces[j];
+    const int sf = f >> 1;
+    if (sf == forced) continue;
+    if (csg_side(G.surf + 10 * sf, G.plane[sf] != 0, x, y, z, u, v, w) != ((f & 1) ? 1 : -1))
+      return false;
   }
   return true;
 }
 
-__device__ __forceinline__ int csg_locate(const Params& P, double x, double y, double z, double u,
-                                          double v, double w) {
-  for (int m = 0; m < P.nvol; ++m)
-    if (csg_holds(P, m, x, y, z, u, v, w, -1)) return m;
+__device__ __forceinline__ int csg_locate(const Geo& G, int nvol, double x, double y, double z,
+                                          double u, double v, double w) {
+  for (int m = 0; m < nvol; ++m)
+    if (csg_holds(G, m, x, y, z, u, v, w, -1)) return m;
   return -1;
 }
 
-// Boundary distance in cell k and the cell entered: the nearest exit over the cell's
-// faces (first face wins ties); entered = the first cell with the crossed surface on
-// the other side whose remaining faces hold at the crossing point, else the first
-// other cell without the crossed surface on the side left that holds it, else none.
-__device__ __forceinline__ double csg_distance(const Params& P, int k, double px, double py,
+// Boundary distance in cell k: the nearest exit over the cell's faces (first face
+// wins ties); *left = the face crossed (surface * 2 + side), -1 if none.
+__device__ __forceinline__ double csg_distance(const Geo& G, int k, double px, double py,
                                                double pz, double dx, double dy, double dz,
-                                               int& next) {
-#pragma clang fp contract(off)
+                                               int& left) {
   double s_min = HUGE_VAL;
-  int left = -1;
-  for (int j = P.face_off[k]; j < P.face_off[k + 1]; ++j) {
-    const int f = P.faces[j];
-    const double t = csg_exit(P.surf + 10 * (f >> 1), px, py, pz, dx, dy, dz, (f & 1) ? 1.0 : -1.0);
+  left = -1;
+  for (int j = G.face_off[k]; j < G.face_off[k + 1]; ++j) {
+    const int f = G.faces[j];
+    const int sf = f >> 1;
+    const double t =
+        csg_exit(G.surf + 10 * sf, G.plane[sf] != 0, px, py, pz, dx, dy, dz, (f & 1) ? 1.0 : -1.0);
     if (t < s_min) {
       s_min = t;
       left = f;
     }
   }
-  next = -1;
-  if (left < 0) return HUGE_VAL;
-  const int s = left >> 1, entered = left ^ 1;
+  return s_min;
+}
+
+// The cell entered through face `left` of cell k at p + s d: the first cell with the
+// crossed surface on the other side whose remaining faces hold at that point, else
+// the first other cell without the crossed surface on the side left that holds it,
+// else none (-1).  Resolved only for steps that end on the boundary.
+__device__ __forceinline__ int csg_next(const Geo& G, int nvol, int k, int left, double px, double py,
+                                        double pz, double dx, double dy, double dz, double s_min) {
+#pragma clang fp contract(off)
+  if (left < 0) return -1;
+  const int sf = left >> 1, entered = left ^ 1;
   const double x = px + s_min * dx, y = py + s_min * dy, z = pz + s_min * dz;
-  for (int j = P.cand_off[entered]; j < P.cand_off[entered + 1]; ++j) {
-    const int m = P.cand[j];
-    if (m != k && csg_holds(P, m, x, y, z, dx, dy, dz, s)) {
-      next = m;
-      return s_min;
-    }
+  for (int j = G.cand_off[entered]; j < G.cand_off[entered + 1]; ++j) {
+    const int m = G.cand[j];
+    if (m != k && csg_holds(G, m, x, y, z, dx, dy, dz, sf)) return m;
   }
-  for (int m = 0; m < P.nvol; ++m) {
+  for (int m = 0; m < nvol; ++m) {
     if (m == k) continue;
     bool has_left = false;
-    for (int j = P.face_off[m]; j < P.face_off[m + 1]; ++j) has_left |= P.faces[j] == left;
-    if (!has_left && csg_holds(P, m, x, y, z, dx, dy, dz, s)) {
-      next = m;
-      return s_min;
-    }
+    for (int j = G.face_off[m]; j < G.face_off[m + 1]; ++j) has_left |= G.faces[j] == left;
+    if (!has_left && csg_holds(G, m, x, y, z, dx, dy, dz, sf)) return m;
   }
-  return s_min;
+  return -1;
 }
 
 __device__ __forceinline__ int locate(const Params& P, double x, double y, double z, double u,
                                       double v, double w) {
-  if (P.gkind == EMS_GEOM_CSG) return csg_locate(P, x, y, z, u, v, w);
+  if (P.gkind == EMS_GEOM_CSG) return csg_locate(global_geo(P), P.nvol, x, y, z, u, v, w);
   if (P.gkind == EMS_GEOM_SLABS) {
     if (fabs(x) > P.hx || fabs(y) > P.hy) return -1;
     for (int j = 0; j < P.nvol; ++j) {
@@ -368,12 +404,19 @@ __device__ __forceinline__ int locate(const Params& P, double x, double y, doubl
 // (-1 = outside the world).  Slabs: z-planes to neighbours, walls |x|,|y| to the
 // outside (ties to the walls).  Shells: outer radius outward, inner radius inward,
 // end caps outside (ties inner, then caps).
+// With quadric cells, `next` holds -2 - (face crossed) until csg_next resolves it.
 template <bool CSG>
-__device__ __forceinline__ double distance(const Params& P, const double* bounds, int vol,
+__device__ __forceinline__ double distance(const Params& P, const Geo& G, int vol,
                                            double px, double py, double pz, double dx, double dy,
                                            double dz, int& next) {
 #pragma clang fp contract(off)
-  if (CSG) return csg_distance(P, vol, px, py, pz, dx, dy, dz, next);
+  if (CSG) {
+    int left;
+    const double sd = csg_distance(G, vol, px, py, pz, dx, dy, dz, left);
+    next = -2 - left;
+    return sd;
+  }
+  const double* bounds = G.bounds;
   double s = HUGE_VAL;
   int nx = -1;
   if (P.gkind == EMS_GEOM_SLABS) {
@@ -485,7 +528,8 @@ __device__ __forceinline__ void mom_diff(double a, double ax, double ay, double 
 // dd/ds = kappa (d_y, -d_x, 0), kappa = 2.99792458 q B_z / p (1/cm, MeV/c, tesla).
 constexpr int kFieldMaxSub = 10000;
 constexpr double kFieldHmin = 1.0e-9;
-constexpr double kFieldVacuumPath = 1000.0;
+constexpr int kFieldVacSub = 256;  // substeps of one step in vacuum
+constexpr uint32_t kVacCaps = 40;  // vacuum steps in a row ending on that cap: a looper
 
 // One classical fourth-order Runge-Kutta step of length h.  The field-step
 // decisions (error against tolerance, chord against boundary) compare differences
@@ -515,23 +559,43 @@ __device__ __forceinline__ void rk4(double kappa, double h, double rx, double ry
   ez = dz + h6 * 0.0;
 }
 
+// Where a curved move stands between substeps: substeps done, trial length of the
+// next substep, path travelled.  nsub = 0 is a move not yet begun.
+struct MoveState {
+  uint32_t nsub;
+  double h, travelled;
+};
+
 // Curved move within volume `vol` for at most s_max (maybe infinite): substeps
 // with step-doubling error control, the boundary searched on each substep's chord
 // and accepted once the chord's sagitta is within tolerance.  Returns 0 at s_max,
-// 1 at a boundary (next set), 2 for a looper (vacuum path cap or substep cap).
+// 1 at a boundary (next set), 2 for a looper in matter (10^4 substeps), 3 when a
+// step in vacuum used its 256 substeps (the step ends there).  The move starts from
+// ms (a move begun earlier continues where it stood) and takes at most `budget`
+// substeps now: when they are used up it returns 4 with ms, the position and the
+// direction holding exactly the loop's state, so that continuing later takes the
+// same substeps, in the same arithmetic, as one uninterrupted move.
 template <bool CSG>
-__device__ __forceinline__ int field_move(const Params& P, const double* bounds, int vol,
+__device__ __forceinline__ int field_move(const Params& P, const Geo& G, int vol,
                                           double kappa, double s_max,
                                           bool vacuum, double& x, double& y, double& z,
                                           double& u, double& v, double& w, double& s_out,
-                                          int& next) {
+                                          int& next, MoveState& ms, uint32_t& budget) {
 #pragma clang fp contract(off)
   const double tol = P.ftol;
-  const double limit = vacuum ? fmin(s_max, kFieldVacuumPath) : s_max;
-  double travelled = 0.0;
-  double h = fabs(kappa) > 0.0 ? fmin(limit, 1.0 / fabs(kappa)) : limit;
+  const double limit = s_max;
+  double travelled = ms.nsub ? ms.travelled : 0.0;
+  double h = ms.nsub ? ms.h : (fabs(kappa) > 0.0 ? fmin(limit, 1.0 / fabs(kappa)) : limit);
   next = -1;
-  for (int nsub = 0; nsub < kFieldMaxSub; ++nsub) {
+  const uint32_t max_sub = vacuum ? kFieldVacSub : kFieldMaxSub;
+  for (uint32_t nsub = ms.nsub; nsub < max_sub; ++nsub) {
+    if (budget == 0u) {  // suspended between substeps
+      ms.nsub = nsub;
+      ms.h = h;
+      ms.travelled = travelled;
+      return 4;
+    }
+    --budget;
     const double hh = fmin(h, limit - travelled);
     double fx, fy, fz, fu, fv, fw, mx, my, mz, mu, mv, mw, px, py, pz, pu, pv, pw;
     rk4(kappa, hh, x, y, z, u, v, w, fx, fy, fz, fu, fv, fw);
@@ -550,7 +614,7 @@ __device__ __forceinline__ int field_move(const Params& P, const double* bounds,
       cx /= L;
       cy /= L;
       cz /= L;
-      sb = distance<CSG>(P, bounds, vol, x, y, z, cx, cy, cz, nx);
+      sb = distance<CSG>(P, G, vol, x, y, z, cx, cy, cz, nx);
     }
     if (sb < L) {
       const double qx = mx - x, qy = my - y, qz = mz - z;
@@ -558,6 +622,7 @@ __device__ __forceinline__ int field_move(const Params& P, const double* bounds,
       const double sx = qx - along * cx, sy = qy - along * cy, sz = qz - along * cz;
       const double sag = sqrt(sx * sx + sy * sy + sz * sz);
       if (sag <= tol || hh <= kFieldHmin) {
+        if (CSG) nx = csg_next(G, P.nvol, vol, -2 - nx, x, y, z, cx, cy, cz, sb);
         const double part = hh * (sb / L);
         double ox, oy, oz, du, dv, dw;
         rk4(kappa, part, x, y, z, u, v, w, ox, oy, oz, du, dv, dw);
@@ -570,6 +635,7 @@ __device__ __forceinline__ int field_move(const Params& P, const double* bounds,
         w = dw / n;
         s_out = travelled + part;
         next = nx;
+        ms.nsub = 0;
         return 1;
       }
       h = fmax(hh * (sb / L), kFieldHmin);
@@ -585,12 +651,14 @@ __device__ __forceinline__ int field_move(const Params& P, const double* bounds,
     travelled += hh;
     if (travelled >= limit) {
       s_out = travelled;
-      return limit < s_max ? 2 : 0;
+      ms.nsub = 0;
+      return 0;
     }
     h = err < tol / 32.0 ? 2.0 * hh : hh;
   }
   s_out = travelled;
-  return 2;
+  ms.nsub = 0;
+  return vacuum ? 3 : 2;
 }
 
 // ------------------------------------------------------------------ track records
@@ -599,6 +667,8 @@ struct Track {
   int sp, vol;
   double x, y, z, u, v, w, T, nlam;
   uint32_t k0, k1, k2, evt, nstep, src;
+  uint32_t vcap;  // field steps in vacuum that ended on their substep cap, in a row
+  MoveState mv;   // a curved move suspended at the end of the last launch (mv.nsub > 0)
 };
 
 struct Sec {
@@ -682,7 +752,8 @@ __device__ __forceinline__ void emit(const Params& P, Emit& o, const Track& t, i
 struct Moved {
   double dep, esc, killed, step_len;
   int limiter, process, escaped;
-  int dest;  // -1 survives, -2 dead, >= 0 queue of its interaction
+  int dest;        // -1 survives, -2 dead, >= 0 queue of its interaction
+  bool suspended;  // the step's curved move ran out of substeps: nothing else happened
 };
 
 // The part of a step before the interaction: interaction length, cross sections,
@@ -690,8 +761,9 @@ struct Moved {
 // escape, process selection (u_1 against Sigma_i(T')), cutoffs.  A track whose
 // step ends in an interaction (or a positron that stops) is sent to a queue with
 // its step count not yet incremented; every other survivor's count is incremented.
-template <class R, bool FIELD, bool CSG>
-__device__ __forceinline__ void transport(const Params& P, const View<R>& V, Track& t, Moved& o) {
+template <class R, bool FIELD, bool CSG, bool MSC>
+__device__ __forceinline__ void transport(const Params& P, const View<R>& V, Track& t, Moved& o,
+                                          uint32_t& budget) {
   const double INF = HUGE_VAL;
   const int sp = t.sp;
   const int m = V.vmat[t.vol];
@@ -733,14 +805,22 @@ __device__ __forceinline__ void transport(const Params& P, const View<R>& V, Tra
   if (FIELD && charged) {  // curved path up to the physics limit; a boundary met first wins
     const double p = sqrt(t.T * (t.T + 2.0 * kMe));
     const double kappa = 2.99792458 * (sp == EMS_ELECTRON ? -1.0 : 1.0) * P.bz / p;
-    const int res = field_move<CSG>(P, V.bounds, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
-                               t.u, t.v, t.w, s, next);
+    const int res = field_move<CSG>(P, V.g, t.vol, kappa, fmin(s_phys, s_cont), !matter, t.x, t.y, t.z,
+                                    t.u, t.v, t.w, s, next, t.mv, budget);
+    if (res == 4) {  // continued next launch: nλ, T, volume and step count untouched
+      o.suspended = true;
+      o.dest = -1;
+      return;
+    }
     lim = res == 1 ? 0 : (res == 2 ? 3 : (s_phys <= s_cont ? 1 : 2));
+    if (res == 3) lim = t.vcap + 1 >= kVacCaps ? 3 : 4;  // 4: vacuum step on its substep cap
+    t.vcap = res == 3 ? t.vcap + 1 : 0;
   } else {
-    const double s_geo = distance<CSG>(P, V.bounds, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
+    const double s_geo = distance<CSG>(P, V.g, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, next);
     if (s_geo <= s_phys && s_geo <= s_cont) {
       lim = 0;
       s = s_geo;
+      if (CSG) next = csg_next(V.g, P.nvol, t.vol, -2 - next, t.x, t.y, t.z, t.u, t.v, t.w, s_geo);
     } else if (s_phys <= s_cont) {
       lim = 1;
       s = s_phys;
@@ -775,6 +855,31 @@ __device__ __forceinline__ void transport(const Params& P, const View<R>& V, Tra
     }
   }
   if (lim != 1 && sigtot > R(0)) t.nlam -= s * (double)sigtot;
+  // multiple scattering of an e-/e+ still moving in matter at the end of the step:
+  // Highland's width theta0 = 13.6 MeV/(beta p) sqrt(s/X0) (1 + 0.038 ln(s/(X0 beta^2)))
+  // at the pre-step energy (0 where the bracket is not positive), space angle
+  // theta0 sqrt(-2 ln u) (at most pi), uniform azimuth
+  if (MSC && charged && matter && s > 0.0 && !stopped && T1 >= P.tcut && lim != 3 &&
+      !(lim == 0 && next < 0)) {
+    const R Tr = (R)T0;
+    const R pm = Px<R>::sq(Tr * (Tr + R(2.0 * 0.51099895)));
+    const R beta = Px<R>::dv(pm, Tr + R(0.51099895));
+    const R r = Px<R>::dv((R)s, Px<R>::x0(V.mat[mm]));
+    const R bracket = R(1) + R(0.038) * Px<R>::lg(Px<R>::dv(r, beta * beta));
+    const R th0 = (r > R(0) && bracket > R(0)) ? Px<R>::dv(R(13.6), beta * pm) * Px<R>::sq(r) * bracket
+                                               : R(0);
+    const R ua = Px<R>::uni(st.word(kMscDraw)), ub = Px<R>::uni(st.word(kMscDraw + 1));
+    R th = th0 * Px<R>::sq(R(-2) * Px<R>::lg(ua));
+    if (th > R(3.14159265358979323846)) th = R(3.14159265358979323846);
+    R sth, cth, sphi, cphi;
+    Px<R>::sc(th, &sth, &cth);
+    Px<R>::sc(R(kTwoPi) * ub, &sphi, &cphi);
+    double nu, nv, nw;
+    rotate(t.u, t.v, t.w, (double)cth, (double)cphi, (double)sphi, nu, nv, nw);
+    t.u = nu;
+    t.v = nv;
+    t.w = nw;
+  }
   t.T = T1;
 
   o.dest = -1;
@@ -823,6 +928,8 @@ __device__ __forceinline__ void transport(const Params& P, const View<R>& V, Tra
       o.killed += t.T;
       o.dest = -2;
     }
+  } else if (o.dest == -2) {
+    t.nstep += 1;  // a track that ends here: its count now includes this step
   }
 }
 
@@ -1011,6 +1118,19 @@ __device__ __forceinline__ unsigned long long* ctr_line(const Params& P, int l) 
 __device__ __forceinline__ uint32_t lo32(unsigned long long v) { return (uint32_t)(v & 0xFFFFFFFFull); }
 __device__ __forceinline__ uint32_t hi32(unsigned long long v) { return (uint32_t)(v >> 32); }
 
+// Kinetic energy of the pool after an iteration, in keV (fixed point): the
+// transport survivors and the interaction outputs add to word kSEnergy of the
+// block's statistics line; the host sums the copies at a synchronisation and
+// admits events against it.
+__device__ __forceinline__ unsigned long long kev(double T) {
+  return (unsigned long long)llrint(T * 1000.0);
+}
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // statistics line of this block
 __device__ __forceinline__ unsigned long long* stat_line(const Params& P) {
   return ctr_line(P, kLStats + (int)(blockIdx.x % kStatCopies));
@@ -1022,9 +1142,11 @@ __device__ __forceinline__ uint32_t queue_size(const Params& P, int q) {
   return (q & 1) ? hi32(v) : lo32(v);
 }
 
-__device__ __forceinline__ uint32_t make_meta(int sp, uint32_t vol) {
-  return (uint32_t)sp | (vol << 6);
+__device__ __forceinline__ uint32_t make_meta(int sp, uint32_t vol, uint32_t vcap = 0u) {
+  return (uint32_t)sp | (vol << 6) | (vcap << kVcapShift);
 }
+// a track whose curved move was suspended: its move state is in fsub, fh, ftrav
+__device__ __forceinline__ bool meta_mid_move(uint32_t meta) { return (meta & (4u | kMidMove)) == kMidMove; }
 __device__ __forceinline__ uint32_t make_pending_meta(int sp, int q, uint32_t vol) {
   return (uint32_t)sp | 4u | ((uint32_t)q << 3) | (vol << 6);
 }
@@ -1032,7 +1154,8 @@ __device__ __forceinline__ uint32_t make_pending_meta(int sp, int q, uint32_t vo
 __device__ __forceinline__ void write_track(const Pool& p, size_t j, int sp, int vol, double x,
                                             double y, double z, double u, double v, double w,
                                             double T, double nlam, uint32_t k0, uint32_t k1,
-                                            uint32_t k2, uint32_t evt, uint32_t nstep) {
+                                            uint32_t k2, uint32_t evt, uint32_t nstep,
+                                            uint32_t vcap = 0u) {
   p.x[j] = x;
   p.y[j] = y;
   p.z[j] = z;
@@ -1046,7 +1169,7 @@ __device__ __forceinline__ void write_track(const Pool& p, size_t j, int sp, int
   p.k2[j] = k2;
   p.evt[j] = evt;
   p.nstep[j] = nstep;
-  p.meta[j] = make_meta(sp, (uint32_t)vol);
+  p.meta[j] = make_meta(sp, (uint32_t)vol, vcap);
 }
 
 // Element offset of pool buffer (class, parity) in the pool set: for every field
@@ -1074,8 +1197,17 @@ enum AggTag : uint32_t {
   kTagAlive = 5,   // index = slot, value = change of the alive count (two's complement)
   kTagEsc = 6,     // index = species * kGrid + bin of the run's escape spectrum
   kTagSteps = 7,   // index = slot * 3 + species: track-steps of the event
-  kTagEvEsc = 8    // index = (slot * 3 + species) * kGrid + bin: the event's escape spectrum
+  kTagEvEsc = 8,   // index = (slot * 3 + species) * kGrid + bin: the event's escape spectrum
+  kTagLife = 9     // index = species * kLifeBins + bin: steps a track took, at its end
 };
+
+// Bin of the number of steps n a track took: 0 for none, else 1 + floor(log2 n),
+// at most kLifeBins - 1.
+__device__ __forceinline__ uint32_t life_bin(uint32_t n) {
+  if (n == 0u) return 0u;
+  const uint32_t b = 32u - (uint32_t)__clz(n);
+  return b < (uint32_t)kLifeBins ? b : (uint32_t)kLifeBins - 1u;
+}
 struct Agg {
   uint32_t key[kAggSlots];
   unsigned long long val[kAggSlots];
@@ -1096,14 +1228,16 @@ __device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsign
   } else if (tag == kTagAlive) {
     const int d = (int)(long long)v;
     const int old = atomicAdd(&P.alive[idx], d);
-    if (old + d == 0) {
-      const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
-      if (k < P.max_events) P.done[k] = idx;
+    if (old + d == 0) {  // the event's last track has ended: it can be read
+      P.slot_state[idx] = 2u;
+      atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
     }
   } else if (tag == kTagEsc) {
     atomicAdd(&P.esc_hist[idx], v);
   } else if (tag == kTagSteps) {
     atomicAdd(&P.ledger[(size_t)(idx / 3u) * kLedger + kLedgerSteps + idx % 3u], v);
+  } else if (tag == kTagLife) {
+    atomicAdd(&P.life_hist[(blockIdx.x % kStatCopies) * kLifeStride + idx], v);
   } else {
     atomicAdd(&P.ev_esc[idx], v);
   }
@@ -1149,9 +1283,15 @@ __host__ __device__ __forceinline__ uint32_t stage_tab_bytes(int n_mats, uint32_
   return (uint32_t)n_mats * 2u * kGrid * kQ * rsize;
 }
 __host__ __device__ __forceinline__ uint32_t align16(uint32_t b) { return (b + 15u) & ~15u; }
-__host__ __device__ __forceinline__ uint32_t stage_bytes(int n_mats, int nvol, uint32_t rsize) {
-  return stage_tab_bytes(n_mats, rsize) + align16(8u * (uint32_t)(nvol + 1)) +
-         2u * align16(4u * (uint32_t)nvol);
+__host__ __device__ __forceinline__ uint32_t stage_bytes(int n_mats, int nvol, uint32_t rsize,
+                                                         int n_surf = 0, int n_faces = 0) {
+  uint32_t b = stage_tab_bytes(n_mats, rsize) + align16(8u * (uint32_t)(nvol + 1)) +
+               2u * align16(4u * (uint32_t)nvol);
+  if (n_surf > 0)  // quadric cells: surfaces, plane flags, face offsets, faces, candidates
+    b += align16(80u * (uint32_t)n_surf) + align16((uint32_t)n_surf) +
+         align16(4u * (uint32_t)(nvol + 1)) + align16(4u * (uint32_t)n_faces) +
+         align16(4u * (uint32_t)(2 * n_surf + 1)) + align16(4u * (uint32_t)n_faces);
+  return b;
 }
 
 extern __shared__ uint4 ems_stage[];  // dynamic LDS of the step kernels
@@ -1190,14 +1330,38 @@ __device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_clas
     V.tab = reinterpret_cast<const R*>(base);
     V.mstride = (int)per;
     V.sp0 = sp0;
-    V.bounds = bnd;
+    V.g = global_geo(P);
+    V.g.bounds = bnd;
     V.vmat = vm;
     V.vbin = vb;
+    if (P.gkind == EMS_GEOM_CSG) {  // the cells' surfaces, faces and candidates too
+      const uint32_t os = oi + align16(4u * (uint32_t)P.nvol);
+      double* sf = reinterpret_cast<double*>(base + os);
+      const uint32_t op = os + align16(80u * (uint32_t)P.n_surf);
+      unsigned char* pl = base + op;
+      const uint32_t ofo = op + align16((uint32_t)P.n_surf);
+      int* fo = reinterpret_cast<int*>(base + ofo);
+      const uint32_t ofa = ofo + align16(4u * (uint32_t)(P.nvol + 1));
+      int* fa = reinterpret_cast<int*>(base + ofa);
+      const uint32_t oco = ofa + align16(4u * (uint32_t)P.n_faces);
+      int* co = reinterpret_cast<int*>(base + oco);
+      const uint32_t oca = oco + align16(4u * (uint32_t)(2 * P.n_surf + 1));
+      int* ca = reinterpret_cast<int*>(base + oca);
+      for (int j = threadIdx.x; j < 10 * P.n_surf; j += kBlock) sf[j] = P.surf[j];
+      for (int j = threadIdx.x; j < P.n_surf; j += kBlock) pl[j] = P.plane[j];
+      for (int j = threadIdx.x; j <= P.nvol; j += kBlock) fo[j] = P.face_off[j];
+      for (int j = threadIdx.x; j < P.n_faces; j += kBlock) {
+        fa[j] = P.faces[j];
+        ca[j] = P.cand[j];
+      }
+      for (int j = threadIdx.x; j <= 2 * P.n_surf; j += kBlock) co[j] = P.cand_off[j];
+      V.g = Geo{bnd, sf, pl, fo, fa, co, ca};
+    }
   } else {
     V.tab = Px<R>::tab(P);
     V.mstride = 3 * kGrid * kQ;
     V.sp0 = 0;
-    V.bounds = P.bounds;
+    V.g = global_geo(P);
     V.vmat = P.vmat;
     V.vbin = P.vbin;
   }
@@ -1211,7 +1375,7 @@ __device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_clas
 // (deferred for lack of output room).  Survivors go to the output pool of their
 // class, tracks that interact to their process queue; both are reserved once per
 // block.
-template <class R, bool FIELD, bool STAGED, bool CSG>
+template <class R, bool FIELD, bool STAGED, bool CSG, bool MSC>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
                                                 uint32_t c, uint32_t nG, uint32_t nC,
@@ -1235,7 +1399,8 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     t.sp = (int)(meta & 3u);
     pending = (meta & 4u) != 0u;
     pq = (int)((meta >> 3) & 7u);
-    vol = meta >> 6;
+    vol = (meta >> 6) & kVolMask;
+    t.vcap = meta >> kVcapShift;
     t.evt = S.evt[io + i];
     t.x = S.x[io + i];
     t.y = S.y[io + i];
@@ -1250,6 +1415,11 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     t.k2 = S.k2[io + i];
     t.nstep = S.nstep[io + i];
     t.src = rec ? S.src[io + i] : 0u;
+    if (FIELD && meta_mid_move(meta)) {
+      t.mv.nsub = S.fsub[io + i];
+      t.mv.h = S.fh[io + i];
+      t.mv.travelled = S.ftrav[io + i];
+    }
   }
   __shared__ MatParams sh_mat[kMaxMat];
   __shared__ Agg sh_agg;
@@ -1273,17 +1443,24 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
         // step's deposit is scored in its pre-step volume
         const uint32_t e = t.evt;
         const double sc = P.scale[e];
+        // substeps of curved moves this lane may take in this launch: a move that
+        // needs more is suspended and continued next launch, so that a wavefront's
+        // time is not set by its one lane with the longest move
+        uint32_t budget = (!FIELD || rec) ? 0xFFFFFFFFu : P.sub_per_step * msteps;
         for (uint32_t m = 0; m < msteps; ++m) {
           const int v0 = t.vol;
           o = Moved{};
           o.process = -1;
           o.dest = -2;
-          transport<R, FIELD, CSG>(P, V, t, o);
+          transport<R, FIELD, CSG, MSC>(P, V, t, o, budget);
+          if (FIELD && o.suspended) break;
           ++nsteps;
+          if (o.limiter == 4) break;  // a capped vacuum step: one per launch
           if (o.dep > 0.0)
             agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)V.vbin[v0]),
                     fixed_point(o.dep, sc));
           if (o.dest != -1) break;
+          if (FIELD && budget == 0u) break;
         }
         stepped = true;
       }
@@ -1304,7 +1481,11 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
         agg_add(P, sh_agg, agg_key(kTagEvEsc, (e * 3u + (uint32_t)t.sp) * kGrid + (uint32_t)b), 1ull);
     }
     if (nsteps) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), nsteps);
-    if (o.dest == -2) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
+    if (o.dest == -2) {
+      agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
+      agg_add(P, sh_agg, agg_key(kTagLife, (uint32_t)t.sp * kLifeBins + life_bin(vol_out ? 0u : t.nstep)),
+              1ull);
+    }
     if (rec && stepped) {
       ems_step_record& r = rec[t.src];
       r.dep = o.dep;
@@ -1336,8 +1517,11 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     wsteps += __shfl_xor(wsteps, off);
     wpos += __shfl_xor(wpos, off);
   }
+  const unsigned long long we = wave_sum64(o.dest == -1 ? kev(t.T) : 0ull);
+  __shared__ unsigned long long sh_e[kW];
   __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
+    sh_e[wave] = we;
     sh_cnt[wave][0] = (uint32_t)__popcll(mS);
 #pragma unroll
     for (int q = 0; q < kNumQueues; ++q) sh_cnt[wave][1 + q] = (uint32_t)__popcll(mq[q]);
@@ -1373,6 +1557,10 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       if (st) atomicAdd(&L[cblk ? kSStepC : kSStepG], (unsigned long long)st);
       if (pos) atomicAdd(&L[kSStepPos], (unsigned long long)pos);
       if (pend) atomicAdd(&L[kSPending], (unsigned long long)pend);
+      unsigned long long e = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < kW; ++w2) e += sh_e[w2];
+      if (e) atomicAdd(&L[kSEnergy], e);
     }
   }
   __syncthreads();  // also completes every lane's score inserts
@@ -1381,8 +1569,14 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     uint32_t j = sh_base[0] + lanes_below(mS, lane);
     for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][0];
     write_track(S, oo + j, t.sp, t.vol, t.x, t.y, t.z, t.u, t.v, t.w, t.T, t.nlam, t.k0, t.k1,
-                t.k2, t.evt, t.nstep);
+                t.k2, t.evt, t.nstep, t.vcap);
     if (rec) S.src[oo + j] = t.src;
+    if (FIELD && o.suspended) {
+      S.meta[oo + j] |= kMidMove;
+      S.fsub[oo + j] = t.mv.nsub;
+      S.fh[oo + j] = t.mv.h;
+      S.ftrav[oo + j] = t.mv.travelled;
+    }
   } else if (o.dest >= 0) {  // interacting track -> its process queue
     const int q = o.dest;
     uint64_t own = mq[0];
@@ -1415,21 +1609,26 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // At least four waves per SIMD without a field (four blocks of 256 per CU): the
 // loop of steps would otherwise take twice the registers of one step; the curved
 // move needs the registers.
-template <class R, bool FIELD, bool STAGED, bool CSG>
+// part: 0 every chunk, 1 the photon chunks only, 2 the charged chunks only (with a
+// field, photons run in a launch of the straight-line variant: the curved-move
+// variant's registers would halve their occupancy).
+template <class R, bool FIELD, bool STAGED, bool CSG, bool MSC>
 __global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
                                                       IQueue Q, ems_step_record* rec,
-                                                      uint32_t msteps) {
+                                                      uint32_t msteps, int part) {
   const unsigned long long a = *ctr_line(P, kLAdmit);
   const uint32_t nG = lo32(a), nC = hi32(a), n = nG + nC;
   const uint32_t nbG = (nG + kBlock - 1) / kBlock, nbC = (nC + kBlock - 1) / kBlock;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
+  if (part != 2 && blockIdx.x == 0 && threadIdx.x == 0 && n) {
     unsigned long long* st = ctr_line(P, kLStats);
     atomicAdd(&st[kSIn], (unsigned long long)n);
     atomicAdd(&st[kSBusy], 1ull);
     atomicMax(&st[kSPeak], (unsigned long long)n);
   }
-  if (blockIdx.x >= nbG + nbC) return;  // (uniform) beyond the work
-  transport_chunk<R, FIELD, STAGED, CSG>(P, S, N, cur, Q, rec, blockIdx.x, nG, nC, nbG, msteps);
+  const uint32_t first = part == 2 ? nbG : 0u, count = part == 0 ? nbG + nbC : (part == 1 ? nbG : nbC);
+  if (blockIdx.x >= count) return;  // (uniform) beyond the work
+  transport_chunk<R, FIELD, STAGED, CSG, MSC>(P, S, N, cur, Q, rec, first + blockIdx.x, nG, nC, nbG,
+                                              msteps);
 }
 
 // Wave-aggregated append of one output stream (parent or secondary j) into the
@@ -1495,7 +1694,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     t.nstep = Q.nstep[j];
     const uint32_t meta = Q.meta[j];
     t.sp = (int)(meta & 3u);
-    t.vol = (int)(meta >> 6);
+    t.vol = (int)((meta >> 6) & kVolMask);
     t.src = Q.src[j];
     t.nlam = -1.0;
     if (put_off) {
@@ -1520,6 +1719,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     if (looped) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(t.T, sc));
     const int delta = (alive ? 1 : 0) + o.nsec - 1;
     if (delta) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)delta);
+    if (!alive) agg_add(P, sh_agg, agg_key(kTagLife, (uint32_t)t.sp * kLifeBins + life_bin(t.nstep)), 1ull);
     if (rec) {
       ems_step_record& r = rec[t.src];
       r.dep += o.dep;
@@ -1545,8 +1745,13 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   __shared__ uint32_t sh_base[2];
   const int wave = threadIdx.x >> 6;
   const uint64_t moff = __ballot(put_off);
+  const unsigned long long we =
+      wave_sum64((h0 ? kev(t.T) : 0ull) + (h1 ? kev(o.s0.T) : 0ull) + (h2 ? kev(o.s1.T) : 0ull) +
+                 (h3 ? kev(o.s2.T) : 0ull));
+  __shared__ unsigned long long sh_e[kW];
   __syncthreads();  // the previous chunk's readers are done with sh_cnt / sh_base
   if (lane == 0) {
+    sh_e[wave] = we;
     sh_cnt[wave][0] = ng0 + ng1 + ng2 + ng3;
     sh_cnt[wave][1] = nc0 + nc1 + nc2 + nc3;
     sh_cnt[wave][2] = (uint32_t)__popcll(moff);
@@ -1568,6 +1773,10 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
 #pragma unroll
     for (int w2 = 0; w2 < kW; ++w2) d += sh_cnt[w2][2];
     if (d) atomicAdd(&stat_line(P)[kSDeferred], (unsigned long long)d);
+    unsigned long long e = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kW; ++w2) e += sh_e[w2];
+    if (e) atomicAdd(&stat_line(P)[kSEnergy], e);
     // the whole capacity in use, no room for any interaction and nothing else in
     // flight: the pool cannot progress
     if (v == 0 && limit == 0 && total > 0 && lo32(so) + hi32(so) == 0 && bound >= N)
@@ -1651,6 +1860,7 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
   ctr[kLAdmit * kLineWords] = out;
   ctr[kLOut * kLineWords] = 0ull;
   ctr[kLOutI * kLineWords] = 0ull;
+  for (int c = 0; c < kStatCopies; ++c) ctr[(kLStats + c) * kLineWords + kSEnergy] = 0ull;
 }
 
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
@@ -1728,22 +1938,27 @@ __global__ void k_enqueue(Queue q, uint32_t tail, const int64_t* off, const uint
 // rest energy; pairs produced later consume what their positrons release), so the
 // fixed-point scale 2^(61 - ceil(log2 E_max)) keeps every sum below 2^61 quanta.
 // Tallies, ledger and escape spectrum zeroed; photons per event counted for the host.
+// One thread per event of a submitted batch: checks its offsets (they must increase
+// within [0, n]; the loop below never leaves that range), zeroes its slot's scores,
+// sets its alive count and fixed-point scale.
 __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots, uint32_t n_events,
-                             const double* T, const int32_t* sp, double* e_in, double* scale,
-                             double* e_row, uint32_t* g_row) {
+                             int64_t n, const double* T, const int32_t* sp, double* e_in,
+                             double* scale, double* e_row, int64_t quarter, unsigned long long* bad) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_events) return;
   const int64_t a = off[e], b = off[e + 1];
+  if (b - a < 1 || a < 0 || b > n) atomicOr(bad, (unsigned long long)kBadEmpty);
+  if (b - a > quarter) atomicOr(bad, (unsigned long long)kBadLarge);
   double s = 0.0, sm = 0.0;
-  uint32_t ng = 0;
-  for (int64_t r = a; r < b; ++r) {
+  const int64_t r0 = a < 0 ? 0 : a, r1 = b > n ? n : b;
+  for (int64_t r = r0; r < r1; ++r) {
     const double t = T[r];
     const int k = sp[r];
     s += t;
     sm += t + (k == EMS_POSITRON ? 2.0 * kMe : 0.0);
-    ng += k == EMS_GAMMA ? 1u : 0u;
   }
   const uint32_t slot = slots[e];
+  P.slot_state[slot] = 1u;
   for (int j = 0; j < P.nbins; ++j) P.tally[(size_t)slot * P.nbins + j] = 0ull;
   for (int j = 0; j < kLedger; ++j) P.ledger[(size_t)slot * kLedger + j] = 0ull;
   if (P.ev_esc)
@@ -1751,8 +1966,7 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
   int ex = 0;
   if (sm > 0.0) frexp(sm, &ex);  // E_max < 2^ex
   e_in[slot] = s;
-  e_row[e] = s;  // per batch row, read back by the host
-  g_row[e] = ng;
+  e_row[e] = s;  // per batch row, read back by the host when it admits by energy
   scale[slot] = ldexp(1.0, 61 - ex);
   P.alive[slot] = (int)(b - a);
 }
@@ -1784,7 +1998,13 @@ __device__ __forceinline__ void copy_track(const Pool& p, size_t from, size_t to
   p.k2[to] = p.k2[from];
   p.evt[to] = p.evt[from];
   p.nstep[to] = p.nstep[from];
-  p.meta[to] = p.meta[from];
+  const uint32_t meta = p.meta[from];
+  p.meta[to] = meta;
+  if (meta_mid_move(meta)) {
+    p.fsub[to] = p.fsub[from];
+    p.fh[to] = p.fh[from];
+    p.ftrav[to] = p.ftrav[from];
+  }
 }
 
 // Histogram of the tracks of both class pools (buffer cur) over the energy grid.
@@ -1896,7 +2116,8 @@ __global__ void k_pool_load(Params P, Pool S, uint32_t N, ems_track_soa s, uint3
   if (!valid) return;
   const size_t k = buf_off(!g, 0, N) + (g ? bg + lanes_below(mg, lane) : bc + lanes_below(mc, lane));
   write_track(S, k, sp, s.vol[j], s.x[j], s.y[j], s.z[j], s.u[j], s.v[j], s.w[j], s.T[j],
-              s.nlam[j], s.k0[j], s.k1[j], s.k2[j], s.event[j], s.nstep[j]);
+              s.nlam[j], s.k0[j], s.k1[j], s.k2[j], s.event[j], s.nstep[j],
+              s.vcap ? s.vcap[j] : 0u);
   S.src[k] = j;
 }
 
@@ -1918,7 +2139,8 @@ __global__ void k_pool_dump(Pool p, ems_track_soa s, uint32_t n, uint32_t off) {
   s.event[j] = p.evt[i];
   s.nstep[j] = p.nstep[i];
   s.species[j] = (int32_t)(p.meta[i] & 3u);
-  s.vol[j] = (int32_t)(p.meta[i] >> 6);
+  s.vol[j] = (int32_t)((p.meta[i] >> 6) & kVolMask);
+  if (s.vcap) s.vcap[j] = p.meta[i] >> kVcapShift;
 }
 
 }  // namespace ems
@@ -1938,16 +2160,30 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   const dim3 gT(blocks_for(bound, kBlock) + 1), gI(blocks_for(bound, kBlock) + kNumQueues);
   const bool field = P.bz != 0.0;
   const bool csg = P.gkind == EMS_GEOM_CSG;
+  const bool msc = P.msc != 0;
   // the run data is staged in LDS when it fits the per-block budget
-  const uint32_t lds = stage_bytes(P.n_mats, P.nvol, mixed ? sizeof(float) : sizeof(double));
+  const uint32_t lds = stage_bytes(P.n_mats, P.nvol, mixed ? sizeof(float) : sizeof(double),
+                                  csg ? P.n_surf : 0, csg ? P.n_faces : 0);
   const bool staged = lds <= kStageMaxBytes;
   const uint32_t sh = staged ? lds : 0u;
-#define EMS_LAUNCH_T(R, F, ST, G) \
-  hipLaunchKernelGGL((k_transport<R, F, ST, G>), gT, b, sh, s, P, S, N, cur, Q, rec, msteps)
-#define EMS_LAUNCH_TG(R, F, ST) \
-  do {                              \
-    if (csg) EMS_LAUNCH_T(R, F, ST, true); \
-    else EMS_LAUNCH_T(R, F, ST, false);    \
+#define EMS_LAUNCH_T(R, F, ST, G, M)                                                       \
+  do {                                                                                     \
+    if (F) {                                                                               \
+      hipLaunchKernelGGL((k_transport<R, false, ST, G, M>), gT, b, sh, s, P, S, N, cur, Q, rec, \
+                         msteps, 1);                                                       \
+      hipLaunchKernelGGL((k_transport<R, F, ST, G, M>), gT, b, sh, s, P, S, N, cur, Q, rec,     \
+                         msteps, 2);                                                       \
+    } else {                                                                               \
+      hipLaunchKernelGGL((k_transport<R, F, ST, G, M>), gT, b, sh, s, P, S, N, cur, Q, rec,     \
+                         msteps, 0);                                                       \
+    }                                                                                      \
+  } while (0)
+#define EMS_LAUNCH_TG(R, F, ST)                    \
+  do {                                             \
+    if (csg && msc) EMS_LAUNCH_T(R, F, ST, true, true);   \
+    else if (csg) EMS_LAUNCH_T(R, F, ST, true, false);    \
+    else if (msc) EMS_LAUNCH_T(R, F, ST, false, true);    \
+    else EMS_LAUNCH_T(R, F, ST, false, false);            \
   } while (0)
   if (mixed) {
     if (field) {
@@ -2000,13 +2236,15 @@ hipError_t launch_enqueue(const Queue& q, uint32_t tail, const int64_t* off, con
 }
 
 hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t* slots,
-                             const double* T, const int32_t* sp, uint32_t n_events, double* e_in,
-                             double* scale, double* e_row, uint32_t* g_row, hipStream_t s) {
+                             const double* T, const int32_t* sp, uint32_t n_events, int64_t n,
+                             double* e_in, double* scale, double* e_row, int64_t quarter,
+                             unsigned long long* bad, hipStream_t s) {
   if (n_events == 0) return hipSuccess;
   hipLaunchKernelGGL(k_event_init, dim3(blocks_for(n_events, 256)), dim3(256), 0, s, P, off, slots,
-                     n_events, T, sp, e_in, scale, e_row, g_row);
+                     n_events, n, T, sp, e_in, scale, e_row, quarter, bad);
   return hipGetLastError();
 }
+
 
 hipError_t launch_spill_hist(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
                              uint32_t nC, unsigned long long* hist, hipStream_t s) {
@@ -2071,37 +2309,205 @@ namespace ems {
 // deposits per bin, then primary energy, escaped, killed, pair conversions,
 // annihilations, track-steps of photons, electrons and positrons; with esc non-null
 // also the events' escape spectra (3 x kGrid counts per row).
+// Rows of a read in the caller's layouts: dep (n x nbins), ledger (n x 5), steps
+// (n x 3), esc (n x 3 x kGrid); a row whose slot is kNoSlot (an id not read) is zero.
 __global__ void k_gather_tallies(Params P, const uint32_t* slots, uint32_t n, const double* e_in,
-                                 double* out, unsigned long long* esc) {
+                                 double* dep, double* ledger, unsigned long long* steps,
+                                 unsigned long long* esc) {
   const uint32_t row = blockIdx.x;
   if (row >= n) return;
   const uint32_t s = slots[row];
-  const double inv = 1.0 / P.scale[s];
-  const uint32_t w = (uint32_t)P.nbins + kRowLedger;
+  const bool ok = s != kNoSlot;
+  const double inv = ok ? 1.0 / P.scale[s] : 0.0;
   for (int b = threadIdx.x; b < P.nbins; b += blockDim.x)
-    out[(size_t)row * w + b] = (double)(long long)P.tally[(size_t)s * P.nbins + b] * inv;
+    dep[(size_t)row * P.nbins + b] = ok ? (double)(long long)P.tally[(size_t)s * P.nbins + b] * inv : 0.0;
   if (esc && P.ev_esc)
     for (int b = threadIdx.x; b < 3 * kGrid; b += blockDim.x)
-      esc[(size_t)row * 3 * kGrid + b] = P.ev_esc[(size_t)s * 3 * kGrid + b];
+      esc[(size_t)row * 3 * kGrid + b] = ok ? P.ev_esc[(size_t)s * 3 * kGrid + b] : 0ull;
   if (threadIdx.x == 0) {
-    double* L = out + (size_t)row * w + P.nbins;
+    double* L = ledger + (size_t)row * 5;
+    unsigned long long* St = steps + (size_t)row * 3;
+    if (!ok) {
+      for (int k = 0; k < 5; ++k) L[k] = 0.0;
+      for (int k = 0; k < 3; ++k) St[k] = 0ull;
+      return;
+    }
     const unsigned long long* G = P.ledger + (size_t)s * kLedger;
     L[0] = e_in[s];
     L[1] = (double)(long long)G[0] * inv;
     L[2] = (double)(long long)G[1] * inv;
     L[3] = (double)G[2];
     L[4] = (double)G[3];
-    L[5] = (double)G[kLedgerSteps];
-    L[6] = (double)G[kLedgerSteps + 1];
-    L[7] = (double)G[kLedgerSteps + 2];
+    for (int k = 0; k < 3; ++k) St[k] = G[kLedgerSteps + k];
   }
 }
 
+// ------------------------------------------------------------------ event slots and ids
+
+struct DeviceCas {
+  __device__ static unsigned long long cas(unsigned long long* p, unsigned long long cmp,
+                                           unsigned long long val) {
+    return atomicCAS(p, cmp, val);
+  }
+};
+
+// Submission: event e of the batch takes the free slot below the top of the stack
+// (top = the host's count of free slots) and enters its id into the table;
+// flag[e] = 1 if it did (a rejected batch removes exactly those entries).
+__global__ void k_slots_take(EvSlots M, uint32_t top, const uint32_t* ids, uint32_t n,
+                             uint32_t* slots, uint32_t* flag, unsigned long long* bad) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint32_t slot = M.free[top - 1u - e];
+  slots[e] = slot;
+  M.id[slot] = ids[e];
+  const int r = map_insert<DeviceCas>(M.map, M.mask, ids[e], slot);
+  flag[e] = r > 0 ? 1u : 0u;
+  if (r == 0) atomicOr(bad, (unsigned long long)kBadDup);
+  if (r < 0) atomicOr(bad, (unsigned long long)kBadMap);
+}
+
+// A rejected batch: its entries are erased and its slots are free again (they never
+// left the stack).
+__global__ void k_slots_undo(EvSlots M, const uint32_t* ids, const uint32_t* slots,
+                             const uint32_t* flag, uint32_t n) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  M.state[slots[e]] = 0u;
+  if (flag[e]) map_erase(M.map, M.mask, ids[e], slots[e]);
+}
+
+// Reset: every slot free (stack = 0 .. n-1, taken from the top), table empty.
+__global__ void k_events_reset(EvSlots M) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= M.mask) M.map[j] = 0ull;
+  if (j < M.n) {
+    M.free[j] = M.n - 1u - j;
+    M.state[j] = 0u;
+    M.claim[j] = kNoSlot;
+  }
+}
+
+// Rebuild the table without its erased entries: clear, then re-enter the id of every
+// slot in use.
+__global__ void k_map_clear(EvSlots M) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= M.mask) M.map[j] = 0ull;
+}
+__global__ void k_map_refill(EvSlots M) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < M.n && M.state[j] != 0u) (void)map_insert<DeviceCas>(M.map, M.mask, M.id[j], j);
+}
+
+// Read, part 1: the slot of each id; a finished slot is claimed by the first
+// position naming it (claim = least position).
+__global__ void k_read_find(EvSlots M, const uint32_t* ids, uint32_t n, uint32_t* slots) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t h = map_find(M.map, M.mask, ids[i]);
+  const uint32_t slot = h == kNoSlot ? kNoSlot : map_slot(M.map, h);
+  slots[i] = slot;
+  if (slot != kNoSlot && M.state[slot] == 2u) atomicMin(&M.claim[slot], i);
+}
+
+// Read, part 2: status of each position (EMS_OK for the claiming position of a
+// finished slot, EMS_NOT_READY for an event in flight, EMS_E_ARG for an unknown id
+// or a repeat); slots[i] = kNoSlot unless read here.
+__global__ void k_read_status(EvSlots M, uint32_t n, uint32_t* slots, int32_t* status) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t slot = slots[i];
+  int32_t st = EMS_E_ARG;
+  if (slot != kNoSlot) {
+    const uint32_t s = M.state[slot];
+    if (s == 2u) st = M.claim[slot] == i ? EMS_OK : EMS_E_ARG;
+    else if (s == 1u) st = EMS_NOT_READY;
+  }
+  status[i] = st;
+  if (st != EMS_OK) slots[i] = kNoSlot;
+}
+
+// A read that failed after part 2: its claims are withdrawn, nothing is released.
+__global__ void k_read_unclaim(EvSlots M, const uint32_t* slots, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && slots[i] != kNoSlot) M.claim[slots[i]] = kNoSlot;
+}
+
+// Read, part 3: release every slot read -- erase its id, free it, push it on the
+// stack at top + (order of arrival).
+__global__ void k_read_release(EvSlots M, const uint32_t* ids, const uint32_t* slots, uint32_t n,
+                               uint32_t top) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t slot = slots[i];
+  if (slot == kNoSlot) return;
+  map_erase(M.map, M.mask, ids[i], slot);
+  M.state[slot] = 0u;
+  M.claim[slot] = kNoSlot;
+  M.free[top + atomicAdd(M.counter, 1u)] = slot;
+}
+
 hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_t n,
-                                 const double* e_in, double* out, unsigned long long* esc,
-                                 hipStream_t s) {
+                                 const double* e_in, double* dep, double* ledger,
+                                 unsigned long long* steps, unsigned long long* esc, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_tallies, dim3(n), dim3(128), 0, s, P, slots, n, e_in, out, esc);
+  hipLaunchKernelGGL(k_gather_tallies, dim3(n), dim3(128), 0, s, P, slots, n, e_in, dep, ledger, steps,
+                     esc);
+  return hipGetLastError();
+}
+
+hipError_t launch_slots_take(const EvSlots& M, uint32_t top, const uint32_t* ids, uint32_t n,
+                             uint32_t* slots, uint32_t* flag, unsigned long long* bad, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slots_take, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, top, ids, n, slots,
+                     flag, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_slots_undo(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
+                             const uint32_t* flag, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slots_undo, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, slots, flag, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_events_reset(const EvSlots& M, hipStream_t s) {
+  const uint64_t n = std::max<uint64_t>((uint64_t)M.mask + 1u, M.n);
+  hipLaunchKernelGGL(k_events_reset, dim3(blocks_for(n, 256)), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_rebuild(const EvSlots& M, hipStream_t s) {
+  hipLaunchKernelGGL(k_map_clear, dim3(blocks_for((uint64_t)M.mask + 1u, 256)), dim3(256), 0, s, M);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_map_refill, dim3(blocks_for(M.n, 256)), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_find(const EvSlots& M, const uint32_t* ids, uint32_t n, uint32_t* slots,
+                            int32_t* status, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_read_find, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, n, slots);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_read_status, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, n, slots, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_unclaim(const EvSlots& M, const uint32_t* slots, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_read_unclaim, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, slots, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_release(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
+                               uint32_t n, uint32_t top, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, M.counter, 1u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_read_release, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, slots, n, top);
   return hipGetLastError();
 }
 

@@ -198,6 +198,7 @@ int build_physics_tables(const ems_material* mats, int n_mats, const ems_physics
     el.atoms = el.rho * kAvogadro / el.A;
     el.electrons = el.Z * el.atoms;
     el.X0 = 716.4 * el.A / (el.Z * (el.Z + 1.0) * std::log(287.0 / std::sqrt(el.Z))) / el.rho;
+    P.X0 = el.X0;
 
     // production thresholds from the range cut
     double Tc = o.tracking_cut, kc = o.tracking_cut;
@@ -264,6 +265,7 @@ int build_physics_tables(const ems_material* mats, int n_mats, const ems_physics
   for (int m = 0; m < n_mats; ++m) {
     mp[m].Tc_f = (float)mp[m].Tc;
     mp[m].kc_f = (float)mp[m].kc;
+    mp[m].X0_f = (float)mp[m].X0;
   }
   return 0;
 }

@@ -1,0 +1,157 @@
+// Randomised checks of the library's event bookkeeping, built on the CPU with
+// AddressSanitizer and UndefinedBehaviorSanitizer by tests/test_sanitize.py:
+//  * the id -> slot table (the probing the kernels run, here with a plain
+//    compare-and-swap) against std::unordered_map, with erased entries left as
+//    tombstones and the table rebuilt as the library does past a quarter of them;
+//  * admission of queued batches (two binary searches per batch) against the same
+//    rule applied event by event.  Energies are integers, so every sum is exact and
+//    both sides must take identical decisions.
+#include <cstdio>
+#include <deque>
+#include <random>
+#include <unordered_map>
+#include <vector>
+
+#define EMS_HD
+#include "ems_batches.h"
+#include "ems_slotmap.h"
+
+struct HostCas {
+  static unsigned long long cas(unsigned long long* p, unsigned long long cmp, unsigned long long val) {
+    const unsigned long long old = *p;
+    if (old == cmp) *p = val;
+    return old;
+  }
+};
+
+static int fuzz_map() {
+  for (uint32_t E : {1u, 7u, 64u, 1000u}) {
+    uint32_t cap = 16;
+    while (cap < 2 * E) cap <<= 1;
+    const uint32_t mask = cap - 1;
+    std::vector<unsigned long long> map(cap, 0ull);
+    std::vector<uint32_t> free_slots, slot_id(E, 0);
+    std::vector<int> used(E, 0);
+    for (uint32_t i = 0; i < E; ++i) free_slots.push_back(E - 1 - i);
+    std::unordered_map<uint32_t, uint32_t> ref;
+    uint64_t tombs = 0;
+    std::mt19937_64 rng(777 + E);
+    const uint32_t id_range = 3 * E + 5;
+    for (int op = 0; op < 200000; ++op) {
+      const uint32_t id = (uint32_t)(rng() % id_range) * 2654435761u;  // colliding homes
+      const int kind = (int)(rng() % 3);
+      if (kind == 0 && !free_slots.empty()) {
+        const uint32_t slot = free_slots.back();
+        const int r = ems::map_insert<HostCas>(map.data(), mask, id, slot);
+        if (r < 0) {
+          std::printf("table full at E=%u\n", E);
+          return 1;
+        }
+        if ((r == 1) != (ref.count(id) == 0)) {
+          std::printf("insert mismatch E=%u op=%d\n", E, op);
+          return 1;
+        }
+        if (r == 1) {
+          ref[id] = slot;
+          slot_id[slot] = id;
+          used[slot] = 1;
+          free_slots.pop_back();
+        }
+      } else if (kind == 1) {
+        const uint32_t h = ems::map_find(map.data(), mask, id);
+        const auto it = ref.find(id);
+        if ((h == ems::kNoSlot) != (it == ref.end()) ||
+            (h != ems::kNoSlot && ems::map_slot(map.data(), h) != it->second)) {
+          std::printf("find mismatch E=%u op=%d\n", E, op);
+          return 1;
+        }
+      } else {
+        const auto it = ref.find(id);
+        if (it == ref.end()) continue;
+        ems::map_erase(map.data(), mask, id, it->second);
+        used[it->second] = 0;
+        free_slots.push_back(it->second);
+        ref.erase(it);
+        if (++tombs * 4 > cap) {  // rebuild: clear, re-enter every slot in use
+          for (auto& v : map) v = 0ull;
+          for (uint32_t s = 0; s < E; ++s)
+            if (used[s] && ems::map_insert<HostCas>(map.data(), mask, slot_id[s], s) != 1) {
+              std::printf("rebuild failed E=%u\n", E);
+              return 1;
+            }
+          tombs = 0;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+struct Ev {
+  int64_t prims;
+  double e;
+};
+
+static int fuzz_batches() {
+  std::mt19937_64 rng(4242);
+  for (int round = 0; round < 300; ++round) {
+    ems::PendingEvents pe;
+    std::deque<Ev> ref;
+    uint64_t n_active = rng() % 50;
+    for (int op = 0; op < 200; ++op) {
+      if (rng() % 3 == 0) {
+        const uint32_t ne = 1 + (uint32_t)(rng() % 40);
+        const bool energy = rng() % 2;
+        std::vector<int64_t> off(ne + 1, 0);
+        std::vector<double> e(ne);
+        for (uint32_t j = 0; j < ne; ++j) {
+          off[j + 1] = off[j] + 1 + (int64_t)(rng() % 6);
+          e[j] = (double)(1 + rng() % 100);
+          ref.push_back({off[j + 1] - off[j], energy ? e[j] : 0.0});
+        }
+        // a batch without energies is admitted by room alone: the reference then
+        // sees zero energies, which never exceed a budget
+        pe.push(off.data(), ne, energy ? e.data() : nullptr);
+      } else {
+        const uint64_t room = rng() % 120;
+        const double e_now = (double)(rng() % 3 == 0 ? 0 : rng() % 200);
+        const double budget = (double)(rng() % 2 == 0 ? 0 : rng() % 400);
+        const ems::Admitted got = pe.admit(n_active, room, e_now, budget);
+        uint64_t m = 0, ev = 0;
+        double ea = 0.0;
+        while (!ref.empty()) {
+          const Ev& x = ref.front();
+          const bool first = n_active + m == 0;
+          if (!first && n_active + m + (uint64_t)x.prims > room) break;
+          const double en = e_now + ea;
+          if (!first && budget > 0.0 && en > 0.0 && x.e > 0.0 && en + x.e > budget) break;
+          m += (uint64_t)x.prims;
+          ea += x.e;
+          ev += 1;
+          ref.pop_front();
+        }
+        if (got.prims != m || got.events != ev || got.energy != ea) {
+          std::printf("admit mismatch round %d op %d: %llu/%llu events, %llu/%llu prims\n", round, op,
+                      (unsigned long long)got.events, (unsigned long long)ev,
+                      (unsigned long long)got.prims, (unsigned long long)m);
+          return 1;
+        }
+        n_active = rng() % 2 ? 0 : n_active + m;
+      }
+      uint64_t rp = 0;
+      for (const Ev& x : ref) rp += (uint64_t)x.prims;
+      if (pe.events() != ref.size() || pe.prims() != rp) {
+        std::printf("queue size mismatch round %d\n", round);
+        return 1;
+      }
+    }
+  }
+  return 0;
+}
+
+int main() {
+  if (fuzz_map() != 0) return 1;
+  if (fuzz_batches() != 0) return 1;
+  std::printf("slots ok\n");
+  return 0;
+}

@@ -56,3 +56,63 @@ def test_barrel_events(orc):
     o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, ev)
     match = np.abs(dep - o["dep"]).max(1) <= 1e-9 * led[:, 0]
     assert match.mean() >= 0.9, match.mean()
+
+
+def test_vacuum_steps_on_their_substep_cap(orc):
+    """Low-momentum e-/e+ in the barrel's vacuum regions: a field step in vacuum ends
+    after 256 substeps (limiter 4, the count of such steps in a row carried with the
+    track) and the 40th in a row kills the track as a looper (limiter 3)."""
+    wl = W.barrel(1)
+    g = wl.geometry
+    n = 4000
+    st = W.random_track_states(n, g.n_vol, 31, e_lo=0.01, e_hi=2.0, bounds=g.bounds, kind=1,
+                               half_z=g.half_z)
+    vac = np.where(g.material < 0)[0]
+    rng = np.random.default_rng(32)
+    st["vol"] = rng.choice(vac, n).astype(np.int32)
+    lo, hi = g.bounds[st["vol"]], g.bounds[st["vol"] + 1]
+    r = lo + (hi - lo) * rng.random(n)
+    a = 2 * np.pi * rng.random(n)
+    st["pos"][:, 0], st["pos"][:, 1] = r * np.cos(a), r * np.sin(a)
+    st["species"] = rng.integers(1, 3, n).astype(np.int32)
+    st["vcap"] = rng.integers(0, 40, n).astype(np.uint32)
+    st["event"] = np.zeros(n, np.uint32)
+    w = orc.World(wl.materials, wl.options, wl.geometry)
+    records, out = _ctx(wl, n).step_once(st)
+    bad = _compare(wl, st, records, out, w.step_tracks(wl.seed, st))
+    assert not bad, f"{len(bad)} of {n} states differ, first {bad[:5]}"
+    lim = set(np.unique(records["limiter"]))
+    assert {3, 4} <= lim
+
+
+def _barrel_run(wl, ev, field_substeps, pool=1 << 20, spill=0):
+    import paper_2203_09467_amd as ems
+    ctx = ems.Context(pool_capacity=pool, max_events=ev.n_events, max_bins=wl.geometry.n_bins,
+                      queue_capacity=ev.n_primaries, seed=wl.seed, spill_capacity=spill,
+                      field_substeps=field_substeps)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    pr = ctx.transport(ems.DeviceEvents(ev), -1)
+    dep, led, status = ctx.read(ev.event_ids)
+    assert (status == 0).all()
+    steps, _, life = ctx.counters(life=True)
+    ctx.close()
+    return dep, led, steps, life, pr
+
+
+def test_suspended_curved_moves_change_no_result():
+    """A curved move that runs out of its launch's substeps is suspended and continued
+    by the next launch where it stood: with 1 substep per step (nearly every move
+    suspended, many times), the default, and 1024 (almost none), every event's
+    tallies, ledger, step counts and steps-per-track histogram are bitwise the same;
+    so they are with a small pool that spills suspended moves to host memory."""
+    wl = W.barrel(16)
+    ev = wl.events
+    ev.energy[:] = np.random.default_rng(5).uniform(200.0, 2000.0, ev.n_events)
+    ref = _barrel_run(wl, ev, 1024)
+    for fs, pool, spill in ((1, 1 << 20, 0), (0, 1 << 20, 0), (2, 1 << 11, 1 << 20)):
+        got = _barrel_run(wl, ev, fs, pool, spill)
+        for a, b in zip(ref[:4], got[:4]):
+            assert np.array_equal(a, b), (fs, pool)
+        if spill:
+            assert got[4].spilled_total > 0
+    assert ref[4].iterations < _barrel_run(wl, ev, 1)[4].iterations

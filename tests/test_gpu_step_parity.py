@@ -61,7 +61,7 @@ def _compare(wl, st, records, out, ores):
                 ok = False
                 continue
             ok &= (out["species"][j] == t.species and out["vol"][j] == t.vol and
-                   out["nstep"][j] == t.nstep)
+                   out["nstep"][j] == t.nstep and out["vcap"][j] == t.vac_caps)
             for f, v in (("x", t.x), ("y", t.y), ("z", t.z)):
                 ok &= abs(out[f][j] - v) <= TOL * max(abs(v), 1.0)
             for f, v in (("u", t.u), ("v", t.v), ("w", t.w)):

@@ -29,8 +29,17 @@ def _run_gpu(wl, events, precision=0, pool=1 << 20, energy_budget=0.0, chunk=Non
     assert pr.alive == 0 and pr.queued_events == 0
     dep, ledger, status = ctx.read(events.event_ids)
     assert (status == 0).all()
-    steps, hist = ctx.counters()
-    return dict(dep=dep, ledger=ledger, steps=steps, esc_hist=hist, progress=pr)
+    steps, hist, life = ctx.counters(life=True)
+    return dict(dep=dep, ledger=ledger, steps=steps, esc_hist=hist, life_hist=life, progress=pr)
+
+
+def _life_bounds(life):
+    b = np.arange(life.shape[1])
+    lo = np.where(b == 0, 0, 2.0 ** (b - 1))
+    hi = np.where(b == 0, 0, 2.0 ** b - 1)
+    life = np.asarray(life, np.float64)
+    top = np.where(life[:, -1] > 0, np.inf, 0.0)  # the last bin has no upper end
+    return life @ lo, life[:, :-1] @ hi[:-1] + top
 
 
 def _ledger_residual(dep, L):
@@ -57,7 +66,8 @@ def _layer_check(g, o, n_batches=20):
 def test_photon_cube_full_size(orc):
     wl = W.photon_cube(10_000)
     g = _run_gpu(wl, wl.events)
-    o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, wl.events, esc_hist=True)
+    o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, wl.events, esc_hist=True,
+                                                                    life_hist=True)
     e_in = o["ledger"][:, 0]
     assert np.abs(_ledger_residual(g["dep"], g["ledger"])).max() < 1e-12
     assert np.array_equal(g["ledger"][:, 0], e_in)
@@ -68,12 +78,25 @@ def test_photon_cube_full_size(orc):
     # escape spectrum: counts per species and log-energy bin
     diff = np.abs(g["esc_hist"].astype(np.float64) - o["esc_hist"]).sum()
     assert diff <= 0.02 * o["esc_hist"].sum() + 2
+    _check_life(g, o)
+
+
+def _check_life(g, o):
+    """Steps-per-track histogram: within what the events that differ can move, and
+    consistent with the GPU's own step counts."""
+    gl = g["life_hist"].astype(np.float64)
+    assert np.abs(gl - o["life_hist"]).sum() <= 0.02 * o["life_hist"].sum() + 2
+    lo, hi = _life_bounds(g["life_hist"])
+    st = g["steps"].astype(np.float64)
+    assert (lo <= st).all() and (st <= hi).all(), (lo, st, hi)
+    assert gl[:, 0].sum() == 0  # every primary starts inside
 
 
 def test_calorimeter_events(orc):
     wl = W.calorimeter(400)
     g = _run_gpu(wl, wl.events)
-    o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, wl.events)
+    o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, wl.events, life_hist=True)
+    _check_life(g, o)
     e_in = o["ledger"][:, 0]
     assert np.abs(_ledger_residual(g["dep"], g["ledger"])).max() < 1e-12
     m = _per_event_match(g["dep"], o["dep"], e_in)
