@@ -79,7 +79,7 @@ typedef struct {
                                per step of one launch (a launch takes up to 4 steps, 32 for
                                a small pool); a move that needs more is suspended and
                                continued by the next launch exactly where it stood, so
-                               results do not depend on it.  0 = 4, at most 1024 */
+                               results do not depend on it.  0 = 2, at most 1024 */
 } ems_config;
 
 /* flags: time every step-kernel launch with HIP events on the launch stream */

@@ -14,10 +14,15 @@
 namespace ems {
 
 struct PendingBatch {
-  std::vector<int64_t> off;  // primaries of event e: off[e] .. off[e+1]-1, off[0] = 0
+  // primaries of event e: off()[e] .. off()[e+1]-1, off()[0] = 0: the caller's array
+  // while it is lent (for the duration of the call that submitted it), else a copy
+  const int64_t* lent = nullptr;
+  std::vector<int64_t> own;
+  uint32_t ne = 0;
   std::vector<double> ecum;  // energy of events [0, e); empty when not tracked
   uint32_t next = 0;         // first event not yet admitted
-  uint32_t n_events() const { return (uint32_t)(off.size() - 1); }
+  uint32_t n_events() const { return ne; }
+  const int64_t* off() const { return lent ? lent : own.data(); }
 };
 
 struct Admitted {
@@ -29,11 +34,14 @@ struct Admitted {
 class PendingEvents {
  public:
   // Queue a batch of ne events (off has ne + 1 entries, off[0] = 0); e, if not
-  // null, holds the kinetic energy of each event.
-  void push(const int64_t* off, uint32_t ne, const double* e) {
+  // null, holds the kinetic energy of each event.  With lend, off is used in place
+  // until keep() is called, which must happen before the caller's array goes away.
+  void push(const int64_t* off, uint32_t ne, const double* e, bool lend = false) {
     if (ne == 0) return;
     PendingBatch b;
-    b.off.assign(off, off + ne + 1);
+    b.ne = ne;
+    if (lend) b.lent = off;
+    else b.own.assign(off, off + ne + 1);
     if (e) {
       b.ecum.resize(ne + 1);
       b.ecum[0] = 0.0;
@@ -54,11 +62,12 @@ class PendingEvents {
     while (!q_.empty()) {
       PendingBatch& b = q_.front();
       const uint32_t a = b.next, n = b.n_events();
+      const int64_t* off = b.off();
       const bool energy = budget > 0.0 && !b.ecum.empty();
       const uint64_t used = n_active + r.prims;
       const double e0 = e_now + r.energy;
       // event a alone
-      const int64_t pa = b.off[a + 1] - b.off[a];
+      const int64_t pa = off[a + 1] - off[a];
       const double ea = energy ? b.ecum[a + 1] - b.ecum[a] : 0.0;
       const bool first = used == 0;
       const bool fits_a = used + (uint64_t)pa <= room && !(energy && e0 > 0.0 && e0 + ea > budget);
@@ -66,8 +75,8 @@ class PendingEvents {
       // events a .. c - 1 with c the end of the longest prefix within both limits
       uint32_t c = a + 1;
       if (used + (uint64_t)pa <= room) {
-        const int64_t lim = b.off[a] + (int64_t)(room - used);
-        c = (uint32_t)(std::upper_bound(b.off.begin() + a + 1, b.off.end(), lim) - b.off.begin()) - 1;
+        const int64_t lim = off[a] + (int64_t)(room - used);
+        c = (uint32_t)(std::upper_bound(off + a + 1, off + n + 1, lim) - off) - 1;
         c = std::max(c, a + 1);
       }
       if (energy && c > a + 1) {
@@ -76,16 +85,25 @@ class PendingEvents {
             (uint32_t)(std::upper_bound(b.ecum.begin() + a + 1, b.ecum.end(), elim) - b.ecum.begin()) - 1;
         c = std::min(c, std::max(ce, a + 1));
       }
-      r.prims += (uint64_t)(b.off[c] - b.off[a]);
+      r.prims += (uint64_t)(off[c] - off[a]);
       r.events += c - a;
       if (!b.ecum.empty()) r.energy += b.ecum[c] - b.ecum[a];
       events_ -= c - a;
-      prims_ -= (uint64_t)(b.off[c] - b.off[a]);
+      prims_ -= (uint64_t)(off[c] - off[a]);
       b.next = c;
       if (c < n) break;  // the next event does not fit
       q_.pop_front();
     }
     return r;
+  }
+
+  // Copy every lent offsets array that is still needed.
+  void keep() {
+    for (PendingBatch& b : q_)
+      if (b.lent) {
+        b.own.assign(b.lent, b.lent + b.ne + 1);
+        b.lent = nullptr;
+      }
   }
 
   uint64_t events() const { return events_; }

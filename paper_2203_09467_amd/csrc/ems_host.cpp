@@ -47,7 +47,7 @@ ems_status fail(ems_status s, const std::string& msg) {
 constexpr size_t kAlign = 256;
 constexpr int kMaxPerSync = 32;
 // curved-move substeps per track-step of a launch (field_substeps = 0)
-constexpr uint32_t kSubPerStep = 4;
+constexpr uint32_t kSubPerStep = 2;
 constexpr uint32_t kMaxVol = 4096;
 constexpr uint32_t kMaxSurf = 4096;
 constexpr uint32_t kMaxFaces = 32768;
@@ -707,7 +707,8 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
     if (badw & kBadDir) m += " direction not a unit vector;";
     return fail(EMS_E_ARG, m);
   }
-  x->pending.push(b->offsets, ne, by_energy ? ev_e.data() : nullptr);
+  // the caller's offsets are used in place until transport_events returns
+  x->pending.push(b->offsets, ne, by_energy ? ev_e.data() : nullptr, true);
   x->n_free -= ne;
   x->q_count += (uint32_t)n;
   return EMS_OK;
@@ -912,8 +913,18 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
 
 extern "C" {
 
+static ems_status transport_events_impl(ems_ctx* x, const ems_event_batch* b, int32_t max_iterations,
+                                        void* stream, ems_progress* progress);
+
 ems_status transport_events(ems_ctx* x, const ems_event_batch* b, int32_t max_iterations,
                             void* stream, ems_progress* progress) {
+  const ems_status st = transport_events_impl(x, b, max_iterations, stream, progress);
+  if (x) x->pending.keep();  // events still queued keep a copy of the batch's offsets
+  return st;
+}
+
+static ems_status transport_events_impl(ems_ctx* x, const ems_event_batch* b, int32_t max_iterations,
+                                        void* stream, ems_progress* progress) {
   if (!x) return fail(EMS_E_ARG, "transport_events: null context");
   if (!x->tables || !x->geometry) return fail(EMS_E_STATE, "transport_events: initialise tables and geometry first");
   hipStream_t s = (hipStream_t)stream;

@@ -1197,8 +1197,7 @@ enum AggTag : uint32_t {
   kTagAlive = 5,   // index = slot, value = change of the alive count (two's complement)
   kTagEsc = 6,     // index = species * kGrid + bin of the run's escape spectrum
   kTagSteps = 7,   // index = slot * 3 + species: track-steps of the event
-  kTagEvEsc = 8,   // index = (slot * 3 + species) * kGrid + bin: the event's escape spectrum
-  kTagLife = 9     // index = species * kLifeBins + bin: steps a track took, at its end
+  kTagEvEsc = 8    // index = (slot * 3 + species) * kGrid + bin: the event's escape spectrum
 };
 
 // Bin of the number of steps n a track took: 0 for none, else 1 + floor(log2 n),
@@ -1207,6 +1206,32 @@ __device__ __forceinline__ uint32_t life_bin(uint32_t n) {
   if (n == 0u) return 0u;
   const uint32_t b = 32u - (uint32_t)__clz(n);
   return b < (uint32_t)kLifeBins ? b : (uint32_t)kLifeBins - 1u;
+}
+
+// The steps-per-track histogram of one block: a few bins take an update from nearly
+// every ending track, so lanes of a wavefront that end in the same bin are counted
+// together (one LDS add per distinct bin and wavefront), and the block adds its
+// non-zero bins to copy blockIdx % kStatCopies once, after its last barrier.
+struct LifeHist {
+  uint32_t n[3 * kLifeBins];
+};
+__device__ __forceinline__ void life_init(LifeHist& L) {
+  for (int j = threadIdx.x; j < 3 * kLifeBins; j += kBlock) L.n[j] = 0u;
+}
+// called by exactly the lanes whose track ends, with bin = species * kLifeBins + life_bin
+__device__ __forceinline__ void life_add(LifeHist& L, uint32_t bin) {
+  uint64_t pend = __ballot(1);
+  while (pend) {
+    const int leader = __builtin_ctzll(pend);
+    const uint32_t k = (uint32_t)__shfl((int)bin, leader);
+    const uint64_t same = __ballot(bin == k);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(&L.n[k], (uint32_t)__popcll(same));
+    pend &= ~same;
+  }
+}
+__device__ __forceinline__ void life_flush(const Params& P, const LifeHist& L) {
+  for (int j = threadIdx.x; j < 3 * kLifeBins; j += kBlock)
+    if (L.n[j]) atomicAdd(&P.life_hist[(blockIdx.x % kStatCopies) * kLifeStride + j], (unsigned long long)L.n[j]);
 }
 struct Agg {
   uint32_t key[kAggSlots];
@@ -1236,8 +1261,6 @@ __device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsign
     atomicAdd(&P.esc_hist[idx], v);
   } else if (tag == kTagSteps) {
     atomicAdd(&P.ledger[(size_t)(idx / 3u) * kLedger + kLedgerSteps + idx % 3u], v);
-  } else if (tag == kTagLife) {
-    atomicAdd(&P.life_hist[(blockIdx.x % kStatCopies) * kLifeStride + idx], v);
   } else {
     atomicAdd(&P.ev_esc[idx], v);
   }
@@ -1423,7 +1446,9 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   }
   __shared__ MatParams sh_mat[kMaxMat];
   __shared__ Agg sh_agg;
+  __shared__ LifeHist sh_life;
   agg_init(sh_agg);
+  life_init(sh_life);
   const View<R> V = stage_view<R, STAGED>(P, cblk, sh_mat);
   // a state that names no species, volume or event slot of this run is dropped
   const bool usable =
@@ -1483,8 +1508,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     if (nsteps) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), nsteps);
     if (o.dest == -2) {
       agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
-      agg_add(P, sh_agg, agg_key(kTagLife, (uint32_t)t.sp * kLifeBins + life_bin(vol_out ? 0u : t.nstep)),
-              1ull);
+      life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(vol_out ? 0u : t.nstep));
     }
     if (rec && stepped) {
       ems_step_record& r = rec[t.src];
@@ -1565,6 +1589,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
   }
   __syncthreads();  // also completes every lane's score inserts
   agg_flush(P, sh_agg);
+  life_flush(P, sh_life);
   if (o.dest == -1) {
     uint32_t j = sh_base[0] + lanes_below(mS, lane);
     for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][0];
@@ -1668,7 +1693,9 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   const uint64_t used = (uint64_t)lo32(so) + hi32(so) + total;
   const uint32_t limit = used < bound ? (uint32_t)((bound - used) / 2) : 0u;
   __shared__ Agg sh_agg;
+  __shared__ LifeHist sh_life;
   agg_init(sh_agg);
+  life_init(sh_life);
   __syncthreads();  // the table is empty before any lane inserts
   const int q = (int)qsel;
   const uint32_t i = (v - start) * kBlock + threadIdx.x;
@@ -1719,7 +1746,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     if (looped) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(t.T, sc));
     const int delta = (alive ? 1 : 0) + o.nsec - 1;
     if (delta) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)delta);
-    if (!alive) agg_add(P, sh_agg, agg_key(kTagLife, (uint32_t)t.sp * kLifeBins + life_bin(t.nstep)), 1ull);
+    if (!alive) life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(t.nstep));
     if (rec) {
       ems_step_record& r = rec[t.src];
       r.dep += o.dep;
@@ -1784,6 +1811,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   }
   __syncthreads();  // also completes every lane's score inserts
   agg_flush(P, sh_agg);
+  life_flush(P, sh_life);
   uint32_t bg = sh_base[0], bc = sh_base[1];
   for (int w2 = 0; w2 < wave; ++w2) {
     bg += sh_cnt[w2][0];

@@ -111,7 +111,26 @@ static int fuzz_batches() {
         }
         // a batch without energies is admitted by room alone: the reference then
         // sees zero energies, which never exceed a budget
-        pe.push(off.data(), ne, energy ? e.data() : nullptr);
+        // half of the batches are lent and kept (copied) before their array goes away
+        const bool lend = rng() % 2;
+        pe.push(off.data(), ne, energy ? e.data() : nullptr, lend);
+        if (lend && rng() % 4 == 0) {  // some admission while lent
+          const ems::Admitted got = pe.admit(n_active, 0, 0.0, 0.0);
+          uint64_t m = 0, ev = 0;
+          double ea = 0.0;
+          while (!ref.empty() && n_active + m == 0) {  // room 0: only a first event goes
+            m += (uint64_t)ref.front().prims;
+            ea += ref.front().e;
+            ev += 1;
+            ref.pop_front();
+          }
+          if (got.prims != m || got.events != ev || got.energy != ea) {
+            std::printf("lent admit mismatch round %d op %d\n", round, op);
+            return 1;
+          }
+          n_active += m;
+        }
+        pe.keep();
       } else {
         const uint64_t room = rng() % 120;
         const double e_now = (double)(rng() % 3 == 0 ? 0 : rng() % 200);

@@ -109,7 +109,7 @@ def test_suspended_curved_moves_change_no_result():
     ev = wl.events
     ev.energy[:] = np.random.default_rng(5).uniform(200.0, 2000.0, ev.n_events)
     ref = _barrel_run(wl, ev, 1024)
-    for fs, pool, spill in ((1, 1 << 20, 0), (0, 1 << 20, 0), (2, 1 << 11, 1 << 20)):
+    for fs, pool, spill in ((1, 1 << 20, 0), (0, 1 << 20, 0), (2, 1 << 9, 1 << 20)):
         got = _barrel_run(wl, ev, fs, pool, spill)
         for a, b in zip(ref[:4], got[:4]):
             assert np.array_equal(a, b), (fs, pool)
