@@ -437,6 +437,9 @@ def main():
                     help="iterations per host synchronisation in the serving loop")
     ap.add_argument("--serve-iters", type=int, default=32,
                     help="step iterations per transport call of the serving loop")
+    ap.add_argument("--barrel-only", choices=["fp64", "mixed"], default=None,
+                    help="only run the barrel (field) workload of --barrel-events primaries in "
+                         "this precision (for profiling the curved-move kernel)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times, "
                          "to scale HBM byte counters")
@@ -459,6 +462,10 @@ def main():
 
     import paper_2203_09467_amd as ems
 
+    if args.barrel_only:
+        p = ems.EMS_FP64 if args.barrel_only == "fp64" else ems.EMS_MIXED
+        print(json.dumps({"barrel_field": run_barrel(ems, args.barrel_events, args, p)}))
+        return
     prec = ems.EMS_FP64 if args.precision == "fp64" else ems.EMS_MIXED
     cpu = None
     keep = 0

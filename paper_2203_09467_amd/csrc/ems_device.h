@@ -79,7 +79,7 @@ struct IQueue {
 enum CounterLine {
   kLOut = 0,      // output pools, survivors of the transport kernel: photons (low), charged (high)
   kLQueue = 1,    // lines 1..4: queue sizes (2i low, 2i+1 high)
-  kLDone = 5,     // finished-event list length (low)
+  kLDone = 5,     // events finished in the interval (low); word 1: check bits of a submitted batch
   kLAdmit = 6,    // admission cursors = pool sizes: photons (low), charged (high)
   kLOutI = 7,     // output pools, tracks written by the interaction kernel (low, high)
   kLStats = 8,    // lines 8 .. 8 + kStatCopies - 1: interval statistics, words kS*
@@ -162,19 +162,22 @@ struct Params {
 };
 
 // Event slots and ids, kept on the device so that submitting and reading a batch
-// costs the host nothing per event.  free: stack of free slots (its height is
-// mirrored by the host); map: open-addressing id -> slot table (power-of-two size,
-// linear probing) of entries (slot + 1) << 32 | id, 0 = empty, kMapTomb = erased;
-// id: the id of each slot; claim: during a read, the first position in the call
-// naming the slot.
+// costs the host nothing per event.  bits: one bit per slot, set while the slot is
+// free (the host mirrors their count); before a batch takes slots, pre[w] = free
+// slots in words [0, w) and the batch takes the lowest free slots in order, so that
+// events submitted together get neighbouring slots in submission order; map:
+// open-addressing id -> slot table (power-of-two size, linear probing) of entries
+// (slot + 1) << 32 | id, 0 = empty, kMapTomb = erased; id: the id of each slot;
+// claim: during a read, the first position in the call naming the slot.
 struct EvSlots {
-  uint32_t* free;
+  uint32_t* bits;
+  uint32_t* pre;      // words + 1 entries
+  uint32_t words;     // ceil(n / 32)
   unsigned long long* map;
   uint32_t mask;
   uint32_t* state;
   uint32_t* id;
   uint32_t* claim;
-  uint32_t* counter;  // pushes onto the free stack during a read
   uint32_t n;         // slots
 };
 // bits of the batch check word set by the submission kernels

@@ -8,7 +8,8 @@
 //   2. K iterations enqueued back to back, each k_iter_begin (pool sizes from the
 //      previous outputs, on the device), k_transport (up to four steps per track),
 //      k_interact (interactions, secondaries, room check);
-//   3. one readback of the counters and the list of events that just finished.
+//   3. one readback of the counters (pool sizes, statistics, the number of events
+//      that finished: the kernels mark their slots on the device).
 // The step count of a track, not the iteration, keys its random numbers, so
 // admission order, put-off interactions and pool size change no result.
 #include <hip/hip_runtime.h>
@@ -221,13 +222,14 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   size_t mcap = 16;
   while (mcap < 2 * E) mcap <<= 1;
   EvSlots ev;
-  ev.free = c.take<uint32_t>(E);
+  ev.words = (uint32_t)((E + 31) / 32);
+  ev.bits = c.take<uint32_t>(ev.words);
+  ev.pre = c.take<uint32_t>((size_t)ev.words + 1);
   ev.map = c.take<unsigned long long>(mcap);
   ev.mask = (uint32_t)(mcap - 1);
   ev.state = c.take<uint32_t>(E);
   ev.id = c.take<uint32_t>(E);
   ev.claim = c.take<uint32_t>(E);
-  ev.counter = c.take<uint32_t>(1);
   ev.n = (uint32_t)E;
   if (!x) return;
   x->set = set;
@@ -670,7 +672,7 @@ ems_status submit(ems_ctx* x, const ems_event_batch* b, hipStream_t s) {
   if (e == hipSuccess) e = hipMemcpyAsync(x->stage_id, b->event_ids, sizeof(uint32_t) * ne, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_zero_u64(bad, 1, s);
   if (e == hipSuccess)
-    e = launch_slots_take(x->slots, x->n_free, x->stage_id, ne, x->stage_slot, x->stage_flag, bad, s);
+    e = launch_slots_take(x->slots, x->stage_id, ne, x->stage_slot, x->stage_flag, bad, s);
   if (e == hipSuccess)
     e = launch_enqueue(x->q, tail, x->stage_off, x->stage_slot, x->stage_id, ne, b->species, b->energy,
                        b->pos, b->dir, (uint32_t)n, bad, s);
@@ -1029,7 +1031,7 @@ ems_status tally_read(ems_ctx* x, uint32_t n, const uint32_t* ids, double* dep, 
       all = all && status[a + j] == EMS_OK;
     }
     if (k) {
-      HIP_OK(launch_read_release(x->slots, x->stage_id, x->stage_slot, m, x->n_free, s));
+      HIP_OK(launch_read_release(x->slots, x->stage_id, x->stage_slot, m, s));
       x->n_free += k;
       x->done_unread -= k;
       x->tombs += k;

@@ -33,8 +33,8 @@ hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t
                              const double* T, const int32_t* sp, uint32_t n_events, int64_t n,
                              double* e_in, double* scale, double* e_row, int64_t quarter,
                              unsigned long long* bad, hipStream_t s);
-hipError_t launch_slots_take(const EvSlots& M, uint32_t top, const uint32_t* ids, uint32_t n,
-                             uint32_t* slots, uint32_t* flag, unsigned long long* bad, hipStream_t s);
+hipError_t launch_slots_take(const EvSlots& M, const uint32_t* ids, uint32_t n, uint32_t* slots,
+                             uint32_t* flag, unsigned long long* bad, hipStream_t s);
 hipError_t launch_slots_undo(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
                              const uint32_t* flag, uint32_t n, hipStream_t s);
 hipError_t launch_events_reset(const EvSlots& M, hipStream_t s);
@@ -43,7 +43,7 @@ hipError_t launch_read_find(const EvSlots& M, const uint32_t* ids, uint32_t n, u
                             int32_t* status, hipStream_t s);
 hipError_t launch_read_unclaim(const EvSlots& M, const uint32_t* slots, uint32_t n, hipStream_t s);
 hipError_t launch_read_release(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
-                               uint32_t n, uint32_t top, hipStream_t s);
+                               uint32_t n, hipStream_t s);
 hipError_t launch_slots_reset(const Params& P, hipStream_t s);
 hipError_t launch_spill_hist(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
                              uint32_t nC, unsigned long long* hist, hipStream_t s);

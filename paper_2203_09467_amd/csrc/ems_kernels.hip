@@ -1633,12 +1633,13 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
 // interaction kernel, which puts off interactions that would not fit).
 // At least four waves per SIMD without a field (four blocks of 256 per CU): the
 // loop of steps would otherwise take twice the registers of one step; the curved
-// move needs the registers.
+// move needs the registers (three waves in mixed precision: +5 % on the barrel;
+// in FP64 the third wave's spills cost more than it gains).
 // part: 0 every chunk, 1 the photon chunks only, 2 the charged chunks only (with a
 // field, photons run in a launch of the straight-line variant: the curved-move
 // variant's registers would halve their occupancy).
 template <class R, bool FIELD, bool STAGED, bool CSG, bool MSC>
-__global__ __launch_bounds__(kBlock, FIELD ? 2 : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
+__global__ __launch_bounds__(kBlock, FIELD ? (sizeof(R) == 4 ? 3 : 2) : 4) void k_transport(Params P, Pool S, uint32_t N, int cur,
                                                       IQueue Q, ems_step_record* rec,
                                                       uint32_t msteps, int part) {
   const unsigned long long a = *ctr_line(P, kLAdmit);
@@ -1986,6 +1987,7 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
     sm += t + (k == EMS_POSITRON ? 2.0 * kMe : 0.0);
   }
   const uint32_t slot = slots[e];
+  if (slot >= P.max_events) return;  // a refused batch (no slot)
   P.slot_state[slot] = 1u;
   for (int j = 0; j < P.nbins; ++j) P.tally[(size_t)slot * P.nbins + j] = 0ull;
   for (int j = 0; j < kLedger; ++j) P.ledger[(size_t)slot * kLedger + j] = 0ull;
@@ -2379,15 +2381,45 @@ struct DeviceCas {
   }
 };
 
-// Submission: event e of the batch takes the free slot below the top of the stack
-// (top = the host's count of free slots) and enters its id into the table;
-// flag[e] = 1 if it did (a rejected batch removes exactly those entries).
-__global__ void k_slots_take(EvSlots M, uint32_t top, const uint32_t* ids, uint32_t n,
-                             uint32_t* slots, uint32_t* flag, unsigned long long* bad) {
+// Submission, part 1 (one block): pre[w] = free slots in the bitmap words [0, w).
+__global__ __launch_bounds__(1024) void k_free_scan(EvSlots M) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x, per = (M.words + 1023u) / 1024u;
+  const uint32_t a = min(M.words, t * per), b = min(M.words, a + per);
+  uint32_t c = 0;
+  for (uint32_t w = a; w < b; ++w) c += (uint32_t)__popc(M.bits[w]);
+  part[t] = c;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024u; off <<= 1) {  // inclusive scan of the parts
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - c;
+  for (uint32_t w = a; w < b; ++w) {
+    M.pre[w] = run;
+    run += (uint32_t)__popc(M.bits[w]);
+  }
+  if (t == 1023u) M.pre[M.words] = part[t];
+}
+
+// Submission, part 2: event e of the batch takes the free slot of rank e -- a batch
+// gets the lowest free slots, in submission order -- and enters its id into the
+// table; flag[e] = 1 if it did (a rejected batch removes exactly those entries).
+__global__ void k_slots_take(EvSlots M, const uint32_t* ids, uint32_t n, uint32_t* slots,
+                             uint32_t* flag, unsigned long long* bad) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const uint32_t slot = M.free[top - 1u - e];
-  slots[e] = slot;
+  // (the host checked that the batch fits the free slots; a rank beyond them would
+  // mean a lost count: the batch is then refused and no kernel touches a slot)
+  const uint32_t slot = e < M.pre[M.words] ? free_slot_of_rank(M.bits, M.pre, M.words, e) : kNoSlot;
+  slots[e] = slot < M.n ? slot : kNoSlot;
+  if (slot >= M.n) {
+    flag[e] = 0u;
+    atomicOr(bad, (unsigned long long)kBadMap);
+    return;
+  }
   M.id[slot] = ids[e];
   const int r = map_insert<DeviceCas>(M.map, M.mask, ids[e], slot);
   flag[e] = r > 0 ? 1u : 0u;
@@ -2395,22 +2427,31 @@ __global__ void k_slots_take(EvSlots M, uint32_t top, const uint32_t* ids, uint3
   if (r < 0) atomicOr(bad, (unsigned long long)kBadMap);
 }
 
-// A rejected batch: its entries are erased and its slots are free again (they never
-// left the stack).
+// Submission, part 3 (after part 2 has read the bitmap): the taken slots leave it.
+__global__ void k_slots_mark(EvSlots M, const uint32_t* slots, uint32_t n) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && slots[e] != kNoSlot) atomicAnd(&M.bits[slots[e] >> 5], ~(1u << (slots[e] & 31u)));
+}
+
+// A rejected batch: its entries are erased and its slots are free again.
 __global__ void k_slots_undo(EvSlots M, const uint32_t* ids, const uint32_t* slots,
                              const uint32_t* flag, uint32_t n) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  if (e >= n || slots[e] == kNoSlot) return;
   M.state[slots[e]] = 0u;
+  atomicOr(&M.bits[slots[e] >> 5], 1u << (slots[e] & 31u));
   if (flag[e]) map_erase(M.map, M.mask, ids[e], slots[e]);
 }
 
-// Reset: every slot free (stack = 0 .. n-1, taken from the top), table empty.
+// Reset: every slot free, table empty.
 __global__ void k_events_reset(EvSlots M) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j <= M.mask) M.map[j] = 0ull;
+  if (j < M.words) {
+    const uint32_t left = M.n - 32u * j;  // slots in this word
+    M.bits[j] = left >= 32u ? 0xFFFFFFFFu : ((1u << left) - 1u);
+  }
   if (j < M.n) {
-    M.free[j] = M.n - 1u - j;
     M.state[j] = 0u;
     M.claim[j] = kNoSlot;
   }
@@ -2461,10 +2502,8 @@ __global__ void k_read_unclaim(EvSlots M, const uint32_t* slots, uint32_t n) {
   if (i < n && slots[i] != kNoSlot) M.claim[slots[i]] = kNoSlot;
 }
 
-// Read, part 3: release every slot read -- erase its id, free it, push it on the
-// stack at top + (order of arrival).
-__global__ void k_read_release(EvSlots M, const uint32_t* ids, const uint32_t* slots, uint32_t n,
-                               uint32_t top) {
+// Read, part 3: release every slot read -- erase its id, free it.
+__global__ void k_read_release(EvSlots M, const uint32_t* ids, const uint32_t* slots, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t slot = slots[i];
@@ -2472,7 +2511,7 @@ __global__ void k_read_release(EvSlots M, const uint32_t* ids, const uint32_t* s
   map_erase(M.map, M.mask, ids[i], slot);
   M.state[slot] = 0u;
   M.claim[slot] = kNoSlot;
-  M.free[top + atomicAdd(M.counter, 1u)] = slot;
+  atomicOr(&M.bits[slot >> 5], 1u << (slot & 31u));
 }
 
 hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_t n,
@@ -2484,11 +2523,17 @@ hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_
   return hipGetLastError();
 }
 
-hipError_t launch_slots_take(const EvSlots& M, uint32_t top, const uint32_t* ids, uint32_t n,
-                             uint32_t* slots, uint32_t* flag, unsigned long long* bad, hipStream_t s) {
+hipError_t launch_slots_take(const EvSlots& M, const uint32_t* ids, uint32_t n, uint32_t* slots,
+                             uint32_t* flag, unsigned long long* bad, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slots_take, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, top, ids, n, slots,
-                     flag, bad);
+  hipLaunchKernelGGL(k_free_scan, dim3(1), dim3(1024), 0, s, M);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slots_take, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, n, slots, flag,
+                     bad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slots_mark, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, slots, n);
   return hipGetLastError();
 }
 
@@ -2500,7 +2545,7 @@ hipError_t launch_slots_undo(const EvSlots& M, const uint32_t* ids, const uint32
 }
 
 hipError_t launch_events_reset(const EvSlots& M, hipStream_t s) {
-  const uint64_t n = std::max<uint64_t>((uint64_t)M.mask + 1u, M.n);
+  const uint64_t n = std::max<uint64_t>((uint64_t)M.mask + 1u, M.n);  // >= words
   hipLaunchKernelGGL(k_events_reset, dim3(blocks_for(n, 256)), dim3(256), 0, s, M);
   return hipGetLastError();
 }
@@ -2530,12 +2575,9 @@ hipError_t launch_read_unclaim(const EvSlots& M, const uint32_t* slots, uint32_t
 }
 
 hipError_t launch_read_release(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
-                               uint32_t n, uint32_t top, hipStream_t s) {
+                               uint32_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, M.counter, 1u);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_read_release, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, slots, n, top);
+  hipLaunchKernelGGL(k_read_release, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, slots, n);
   return hipGetLastError();
 }
 

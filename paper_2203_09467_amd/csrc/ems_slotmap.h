@@ -76,4 +76,39 @@ EMS_HD inline void map_erase(unsigned long long* map, uint32_t mask, uint32_t id
   }
 }
 
+// Free slots are the set bits of a bitmap; pre[w] counts the set bits of words
+// [0, w).  The free slot of rank r (0-based, in increasing slot order) is in the
+// word w with pre[w] <= r < pre[w + 1], at the bit of rank r - pre[w] within it.
+
+// Index (0..31) of the set bit of rank r in x (r < popcount(x)): binary descent on
+// the popcounts of the low halves.
+EMS_HD inline uint32_t bit_select(uint32_t x, uint32_t r) {
+  uint32_t pos = 0;
+  for (uint32_t half = 16; half > 0; half >>= 1) {
+    const uint32_t low = x & ((1u << half) - 1u);
+    const uint32_t c = (uint32_t)__builtin_popcount(low);
+    if (r >= c) {
+      r -= c;
+      x >>= half;
+      pos += half;
+    } else {
+      x = low;
+    }
+  }
+  return pos;
+}
+
+// Slot of free rank r given the bitmap and its word prefix counts (words + 1
+// entries); r must be below pre[words].
+EMS_HD inline uint32_t free_slot_of_rank(const uint32_t* bits, const uint32_t* pre, uint32_t words,
+                                         uint32_t r) {
+  uint32_t lo = 0, hi = words;  // pre[lo] <= r < pre[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  return lo * 32u + bit_select(bits[lo], r - pre[lo]);
+}
+
 }  // namespace ems

@@ -3,12 +3,15 @@
 //  * the id -> slot table (the probing the kernels run, here with a plain
 //    compare-and-swap) against std::unordered_map, with erased entries left as
 //    tombstones and the table rebuilt as the library does past a quarter of them;
+//  * the free-slot bitmap (a batch takes the lowest free slots in order) against a
+//    std::set;
 //  * admission of queued batches (two binary searches per batch) against the same
 //    rule applied event by event.  Energies are integers, so every sum is exact and
 //    both sides must take identical decisions.
 #include <cstdio>
 #include <deque>
 #include <random>
+#include <set>
 #include <unordered_map>
 #include <vector>
 
@@ -83,6 +86,73 @@ static int fuzz_map() {
         }
       }
     }
+  }
+  return 0;
+}
+
+// The free-slot bitmap: a batch takes the slots of free ranks 0 .. ne-1, i.e. the
+// ne lowest free slots in increasing order (the reference is a std::set).
+static int fuzz_bitmap() {
+  std::mt19937_64 rng(99);
+  for (uint32_t n : {1u, 31u, 32u, 33u, 100u, 1000u}) {
+    const uint32_t words = (n + 31) / 32;
+    std::vector<uint32_t> bits(words, 0u), pre(words + 1, 0u);
+    std::set<uint32_t> ref;
+    for (uint32_t j = 0; j < n; ++j) {
+      bits[j / 32] |= 1u << (j % 32);
+      ref.insert(j);
+    }
+    std::vector<uint32_t> taken;
+    for (int op = 0; op < 20000; ++op) {
+      if (rng() % 2 == 0) {
+        const uint32_t ne = ref.empty() ? 0 : 1 + (uint32_t)(rng() % ref.size());
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < words; ++w) {
+          pre[w] = run;
+          run += (uint32_t)__builtin_popcount(bits[w]);
+        }
+        pre[words] = run;
+        if (run != ref.size()) {
+          std::printf("bitmap count mismatch n=%u\n", n);
+          return 1;
+        }
+        std::vector<uint32_t> got;
+        for (uint32_t e = 0; e < ne; ++e) got.push_back(ems::free_slot_of_rank(bits.data(), pre.data(), words, e));
+        auto it = ref.begin();
+        for (uint32_t e = 0; e < ne; ++e, ++it)
+          if (got[e] != *it) {
+            std::printf("bitmap take mismatch n=%u op=%d e=%u: %u vs %u\n", n, op, e, got[e], *it);
+            return 1;
+          }
+        for (uint32_t g : got) {
+          bits[g / 32] &= ~(1u << (g % 32));
+          ref.erase(g);
+          taken.push_back(g);
+        }
+      } else if (!taken.empty()) {
+        const size_t k = 1 + rng() % taken.size();
+        for (size_t j = 0; j < k; ++j) {
+          const size_t i = rng() % taken.size();
+          const uint32_t g = taken[i];
+          taken[i] = taken.back();
+          taken.pop_back();
+          bits[g / 32] |= 1u << (g % 32);
+          ref.insert(g);
+        }
+      }
+    }
+  }
+  for (uint32_t x = 1; x != 0; x = x * 2654435761u + 12345u) {  // bit_select on assorted words
+    if (x > 0xFFFF0000u) break;
+    uint32_t r = 0;
+    for (uint32_t b = 0; b < 32; ++b)
+      if (x >> b & 1u) {
+        if (ems::bit_select(x, r) != b) {
+          std::printf("bit_select(%08x, %u) != %u\n", x, r, b);
+          return 1;
+        }
+        ++r;
+      }
   }
   return 0;
 }
@@ -171,6 +241,7 @@ static int fuzz_batches() {
 int main() {
   if (fuzz_map() != 0) return 1;
   if (fuzz_batches() != 0) return 1;
+  if (fuzz_bitmap() != 0) return 1;
   std::printf("slots ok\n");
   return 0;
 }
