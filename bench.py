@@ -423,9 +423,9 @@ def main():
     ap.add_argument("--no-photon-sat", action="store_true",
                     help="skip the photon-cube runs at 1e6 and 1e7 primaries")
     ap.add_argument("--serve-events", type=int, default=1000)
-    ap.add_argument("--serve-budget", type=float, default=0.0,
-                    help="energy in flight of the serving loop, MeV (0: admission by free "
-                         "pool slots only)")
+    ap.add_argument("--serve-budget", type=float, default=1e8,
+                    help="kinetic energy of the pool (measured on the device) up to which the "
+                         "serving loop admits events, MeV, besides free pool slots (0: slots only)")
     ap.add_argument("--serve-spill", type=int, default=1 << 23,
                     help="tracks the serving context may spill to pinned host memory")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
@@ -544,9 +544,10 @@ def main():
                           "workload": "calorimeter geometry; events of U{1..500} primaries "
                                       "(60/20/20% e-/e+/photon), log-uniform 1-100 GeV, seed 5"}
         out["serving"]["admission"] = ("by free pool slots (a quarter of the pool for new "
-                                       "primaries), energy budget "
-                                       f"{args.serve_budget:g} MeV (0 = none); a pool above 3/4 "
-                                       "full spills its highest-energy tracks to host memory "
+                                       "primaries) while the pool's kinetic energy, measured on "
+                                       f"the device, stays within {args.serve_budget:g} MeV "
+                                       "(0 = slots only); a pool above 3/4 full spills its "
+                                       "highest-energy tracks to host memory "
                                        f"(room for {args.serve_spill} tracks)")
         highs = [float(x) for x in args.serve_rates_high.split(",") if x.strip()]
         out["serving"]["higher_loads"] = [
