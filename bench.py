@@ -254,6 +254,30 @@ def characterise(log):
             "interactions_per_iteration_at_peak": int(log["interactions"][k_peak])}
 
 
+def run_serving_batch(ems, args, precision):
+    """The serving workload's events submitted at once and run to completion (the
+    batch rate of the same events, against which the serving loop saturates)."""
+    import torch
+    import workloads as W
+    wl = W.serving(n_events=args.serve_events, rate_hz=args.serve_rate)
+    ctx = ems.Context(pool_capacity=args.pool, max_events=args.serve_events,
+                      max_bins=wl.geometry.n_bins, queue_capacity=wl.events.n_primaries,
+                      seed=wl.seed, precision=precision, energy_budget=args.serve_budget,
+                      iterations_per_sync=args.serve_per_sync, spill_capacity=args.serve_spill)
+    ctx.setup(wl.materials, wl.options, wl.geometry)
+    dev = ems.DeviceEvents(wl.events)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr = ctx.transport(dev, -1)
+    dep, led, status = ctx.read(wl.events.event_ids)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.close()
+    assert (status == 0).all()
+    return {"track_steps_per_s": pr.track_steps / t, "wall_s": t, "iterations": pr.iterations,
+            "peak_tracks_in_flight": pr.peak_alive}
+
+
 def run_serving(ems, args, precision, rate=None):
     from paper_2203_09467_amd.serve import serve
     import workloads as W
@@ -549,6 +573,9 @@ def main():
                                        "(0 = slots only); a pool above 3/4 full spills its "
                                        "highest-energy tracks to host memory "
                                        f"(room for {args.serve_spill} tracks)")
+        out["serving"]["same_events_as_one_batch"] = {
+            "fp64": run_serving_batch(ems, args, ems.EMS_FP64),
+            "note": "the 1000 events submitted at once and run to completion, same admission"}
         highs = [float(x) for x in args.serve_rates_high.split(",") if x.strip()]
         out["serving"]["higher_loads"] = [
             {"offered_rate_hz": r2, "fp64": run_serving(ems, args, ems.EMS_FP64, r2),

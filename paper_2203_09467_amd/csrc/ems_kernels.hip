@@ -1739,7 +1739,11 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   if (valid) {
     const uint32_t e = t.evt;
     const double sc = P.scale[e];
-    if (o.dep > 0.0)
+    // every local deposit is scored, a negative one too: a product sampled in FP32 a
+    // hair below its kinematic limit (pair production just above threshold) gets a
+    // kinetic energy of about -1e-7 of its rest energy, balanced exactly by its
+    // partner's; dropping it would create that energy
+    if (o.dep != 0.0)
       agg_add(P, sh_agg, agg_key(kTagTally, e * (uint32_t)P.nbins + (uint32_t)P.vbin[t.vol]),
               fixed_point(o.dep, sc));
     if (o.n_pair) agg_add(P, sh_agg, agg_key(kTagLedger + 2, e), (unsigned long long)o.n_pair);
