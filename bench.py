@@ -453,7 +453,7 @@ def main():
     ap.add_argument("--serve-spill", type=int, default=1 << 23,
                     help="tracks the serving context may spill to pinned host memory")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered events/s")
-    ap.add_argument("--serve-rates-high", type=str, default="120,200",
+    ap.add_argument("--serve-rates-high", type=str, default="120,200,400",
                     help="higher offered loads (events/s, comma separated); empty skips them")
     ap.add_argument("--no-csg", action="store_true", help="skip the quadric-cell geometry runs")
     ap.add_argument("--csg-events", type=int, default=20_000)

@@ -108,6 +108,13 @@ constexpr int kLineWords = 32;  // 64-bit words per line
 // (a block adds to copy blockIdx % kStatCopies): its few bins take an update from
 // nearly every block
 constexpr int kLifeStride = 64;
+// Per-event scores (tally bins, ledger words, alive count) are kept in kEvCopies
+// copies; a block adds to copy blockIdx % kEvCopies.  An event's tracks can fill
+// most blocks of an iteration (serving: hundreds of primaries per event), and one
+// copy per event took every block's atomic on the same few addresses.  Reads sum
+// the copies; an event is finished when its copies' alive counts sum to zero,
+// checked after each iteration.
+constexpr int kEvCopies = 8;
 
 struct MatParams {
   double Tc, kc;      // production thresholds (delta rays, brems photons)

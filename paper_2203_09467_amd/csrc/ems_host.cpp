@@ -183,9 +183,9 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   int* gfaces = c.take<int>(kMaxFaces);
   int* gcoff = c.take<int>(2 * kMaxSurf + 1);
   int* gcand = c.take<int>(kMaxFaces);
-  unsigned long long* tally = c.take<unsigned long long>(E * B);
-  unsigned long long* ledger = c.take<unsigned long long>(E * kLedger);
-  int* alive = c.take<int>(E);
+  unsigned long long* tally = c.take<unsigned long long>(E * kEvCopies * B);
+  unsigned long long* ledger = c.take<unsigned long long>(E * kEvCopies * kLedger);
+  int* alive = c.take<int>(E * kEvCopies);
   double* scale = c.take<double>(E);
   double* e_in = c.take<double>(E);
   unsigned long long* ctr = c.take<unsigned long long>(kNumLines * kLineWords);

@@ -1246,21 +1246,18 @@ __device__ __forceinline__ uint32_t agg_key(uint32_t tag, uint32_t index) {
 // puts its event slot on the finished list.
 __device__ __forceinline__ void agg_global(const Params& P, uint32_t key, unsigned long long v) {
   const uint32_t tag = key >> kAggIndexBits, idx = key & ((1u << kAggIndexBits) - 1u);
+  const uint32_t copy = blockIdx.x % kEvCopies;
   if (tag == kTagTally) {
-    atomicAdd(&P.tally[idx], v);
+    const uint32_t e = idx / (uint32_t)P.nbins, b = idx % (uint32_t)P.nbins;
+    atomicAdd(&P.tally[((size_t)e * kEvCopies + copy) * P.nbins + b], v);
   } else if (tag < kTagAlive) {
-    atomicAdd(&P.ledger[(size_t)idx * kLedger + (tag - kTagLedger)], v);
+    atomicAdd(&P.ledger[((size_t)idx * kEvCopies + copy) * kLedger + (tag - kTagLedger)], v);
   } else if (tag == kTagAlive) {
-    const int d = (int)(long long)v;
-    const int old = atomicAdd(&P.alive[idx], d);
-    if (old + d == 0) {  // the event's last track has ended: it can be read
-      P.slot_state[idx] = 2u;
-      atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
-    }
+    atomicAdd(&P.alive[(size_t)idx * kEvCopies + copy], (int)(long long)v);
   } else if (tag == kTagEsc) {
     atomicAdd(&P.esc_hist[idx], v);
   } else if (tag == kTagSteps) {
-    atomicAdd(&P.ledger[(size_t)(idx / 3u) * kLedger + kLedgerSteps + idx % 3u], v);
+    atomicAdd(&P.ledger[((size_t)(idx / 3u) * kEvCopies + copy) * kLedger + kLedgerSteps + idx % 3u], v);
   } else {
     atomicAdd(&P.ev_esc[idx], v);
   }
@@ -1896,6 +1893,20 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
   for (int c = 0; c < kStatCopies; ++c) ctr[(kLStats + c) * kLineWords + kSEnergy] = 0ull;
 }
 
+// After an iteration: an event in flight whose alive copies sum to zero has no
+// track left anywhere (pool, queues, host spill): it is finished and can be read.
+__global__ void k_done_scan(Params P) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.max_events || P.slot_state[e] != 1u) return;
+  int a = 0;
+#pragma unroll
+  for (int c = 0; c < kEvCopies; ++c) a += P.alive[(size_t)e * kEvCopies + c];
+  if (a == 0) {
+    P.slot_state[e] = 2u;
+    atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
+  }
+}
+
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
 // charged pool at the admission cursors (one atomic per wavefront and class).
 __global__ void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur, uint32_t head, uint32_t m) {
@@ -1993,8 +2004,8 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
   const uint32_t slot = slots[e];
   if (slot >= P.max_events) return;  // a refused batch (no slot)
   P.slot_state[slot] = 1u;
-  for (int j = 0; j < P.nbins; ++j) P.tally[(size_t)slot * P.nbins + j] = 0ull;
-  for (int j = 0; j < kLedger; ++j) P.ledger[(size_t)slot * kLedger + j] = 0ull;
+  for (int j = 0; j < kEvCopies * P.nbins; ++j) P.tally[(size_t)slot * kEvCopies * P.nbins + j] = 0ull;
+  for (int j = 0; j < kEvCopies * kLedger; ++j) P.ledger[(size_t)slot * kEvCopies * kLedger + j] = 0ull;
   if (P.ev_esc)
     for (int j = 0; j < 3 * kGrid; ++j) P.ev_esc[(size_t)slot * 3 * kGrid + j] = 0ull;
   int ex = 0;
@@ -2002,7 +2013,8 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
   e_in[slot] = s;
   e_row[e] = s;  // per batch row, read back by the host when it admits by energy
   scale[slot] = ldexp(1.0, 61 - ex);
-  P.alive[slot] = (int)(b - a);
+  P.alive[(size_t)slot * kEvCopies] = (int)(b - a);
+  for (int c = 1; c < kEvCopies; ++c) P.alive[(size_t)slot * kEvCopies + c] = 0;
 }
 
 // ------------------------------------------------------------------ spilling to host memory
@@ -2114,10 +2126,11 @@ __global__ void k_unspill(Params P, Pool S, uint32_t N, int cur, uint32_t m) {
 __global__ void k_slots_reset(Params P) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.max_events) return;
-  P.alive[e] = 1 << 30;
+  P.alive[(size_t)e * kEvCopies] = 1 << 30;
+  for (int c = 1; c < kEvCopies; ++c) P.alive[(size_t)e * kEvCopies + c] = 0;
   const_cast<double*>(P.scale)[e] = 0x1p40;
-  for (int b = 0; b < P.nbins; ++b) P.tally[(size_t)e * P.nbins + b] = 0ull;
-  for (int b = 0; b < kLedger; ++b) P.ledger[(size_t)e * kLedger + b] = 0ull;
+  for (int b = 0; b < kEvCopies * P.nbins; ++b) P.tally[(size_t)e * kEvCopies * P.nbins + b] = 0ull;
+  for (int b = 0; b < kEvCopies * kLedger; ++b) P.ledger[(size_t)e * kEvCopies * kLedger + b] = 0ull;
   if (P.ev_esc)
     for (int b = 0; b < 3 * kGrid; ++b) P.ev_esc[(size_t)e * 3 * kGrid + b] = 0ull;
 }
@@ -2242,6 +2255,9 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   if (e != hipSuccess) return e;
   if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
   else hipLaunchKernelGGL(k_interact<double>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_done_scan, dim3(blocks_for(P.max_events, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 
@@ -2353,8 +2369,12 @@ __global__ void k_gather_tallies(Params P, const uint32_t* slots, uint32_t n, co
   const uint32_t s = slots[row];
   const bool ok = s != kNoSlot;
   const double inv = ok ? 1.0 / P.scale[s] : 0.0;
-  for (int b = threadIdx.x; b < P.nbins; b += blockDim.x)
-    dep[(size_t)row * P.nbins + b] = ok ? (double)(long long)P.tally[(size_t)s * P.nbins + b] * inv : 0.0;
+  for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) {
+    unsigned long long t = 0;
+    if (ok)
+      for (int c = 0; c < kEvCopies; ++c) t += P.tally[((size_t)s * kEvCopies + c) * P.nbins + b];
+    dep[(size_t)row * P.nbins + b] = ok ? (double)(long long)t * inv : 0.0;
+  }
   if (esc && P.ev_esc)
     for (int b = threadIdx.x; b < 3 * kGrid; b += blockDim.x)
       esc[(size_t)row * 3 * kGrid + b] = ok ? P.ev_esc[(size_t)s * 3 * kGrid + b] : 0ull;
@@ -2366,7 +2386,11 @@ __global__ void k_gather_tallies(Params P, const uint32_t* slots, uint32_t n, co
       for (int k = 0; k < 3; ++k) St[k] = 0ull;
       return;
     }
-    const unsigned long long* G = P.ledger + (size_t)s * kLedger;
+    unsigned long long G[kLedger];
+    for (int k = 0; k < kLedger; ++k) {
+      G[k] = 0ull;
+      for (int c = 0; c < kEvCopies; ++c) G[k] += P.ledger[((size_t)s * kEvCopies + c) * kLedger + k];
+    }
     L[0] = e_in[s];
     L[1] = (double)(long long)G[0] * inv;
     L[2] = (double)(long long)G[1] * inv;
