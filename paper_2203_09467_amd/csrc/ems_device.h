@@ -113,7 +113,7 @@ constexpr int kLifeStride = 64;
 // most blocks of an iteration (serving: hundreds of primaries per event), and one
 // copy per event took every block's atomic on the same few addresses.  Reads sum
 // the copies; an event is finished when its copies' alive counts sum to zero,
-// checked after each iteration.
+// checked once per host synchronisation (the host reads completions only then).
 constexpr int kEvCopies = 8;
 
 struct MatParams {

@@ -623,9 +623,6 @@ ems_status init_geometry(ems_ctx* x, const ems_geometry* g, void* stream) {
 
 namespace {
 
-// Submit a batch: slots, ring copy, slot initialisation.  Nothing changes on error.
-// The host work per event is a few array updates and one hash insert; per-event
-// sums (energy, photons) are made on the device.
 // The device slot state after creation or a reset.
 ems_status ensure_events(ems_ctx* x, hipStream_t s) {
   if (!x->ev_reset) return EMS_OK;
@@ -847,6 +844,7 @@ ems_status run_interval(ems_ctx* x, hipStream_t s, ems_step_record* rec, int ite
     if (x->ev[2 * j + 1]) HIP_OK(hipEventRecord(x->ev[2 * j + 1], s));
     x->cur = 1 - x->cur;
   }
+  HIP_OK(launch_done_scan(x->P, s));  // events finished during the interval
   HIP_OK(hipMemcpyAsync(x->h_ctr, x->ctr, kNumLines * kLineWords * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   uint32_t ilog[4 * kMaxPerSync];

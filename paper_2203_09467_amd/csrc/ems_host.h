@@ -45,6 +45,7 @@ hipError_t launch_read_unclaim(const EvSlots& M, const uint32_t* slots, uint32_t
 hipError_t launch_read_release(const EvSlots& M, const uint32_t* ids, const uint32_t* slots,
                                uint32_t n, hipStream_t s);
 hipError_t launch_slots_reset(const Params& P, hipStream_t s);
+hipError_t launch_done_scan(const Params& P, hipStream_t s);
 hipError_t launch_spill_hist(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,
                              uint32_t nC, unsigned long long* hist, hipStream_t s);
 hipError_t launch_spill_split(const Params& P, const Pool& S, uint32_t N, int cur, uint32_t nG,

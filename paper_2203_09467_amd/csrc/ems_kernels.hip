@@ -1893,8 +1893,9 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
   for (int c = 0; c < kStatCopies; ++c) ctr[(kLStats + c) * kLineWords + kSEnergy] = 0ull;
 }
 
-// After an iteration: an event in flight whose alive copies sum to zero has no
-// track left anywhere (pool, queues, host spill): it is finished and can be read.
+// Before the host reads the counters of a sync interval: an event in flight whose
+// alive copies sum to zero has no track left anywhere (pool, queues, host spill):
+// it is finished and can be read.
 __global__ void k_done_scan(Params P) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.max_events || P.slot_state[e] != 1u) return;
@@ -2255,8 +2256,10 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
   if (e != hipSuccess) return e;
   if (mixed) hipLaunchKernelGGL(k_interact<float>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
   else hipLaunchKernelGGL(k_interact<double>, gI, b, 0, s, P, Q, S, N, cur, rec, bound);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_done_scan(const Params& P, hipStream_t s) {
   hipLaunchKernelGGL(k_done_scan, dim3(blocks_for(P.max_events, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
