@@ -1502,10 +1502,13 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
       if (P.ev_esc)
         agg_add(P, sh_agg, agg_key(kTagEvEsc, (e * 3u + (uint32_t)t.sp) * kGrid + (uint32_t)b), 1ull);
     }
-    if (nsteps) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), nsteps);
     if (o.dest == -2) {
+      // the track ends: its step count (one per step, including steps that ended in
+      // an interaction) goes to the event's track-steps of its species once
+      const uint32_t n = vol_out ? 0u : t.nstep;
       agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)-1);
-      life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(vol_out ? 0u : t.nstep));
+      if (n) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), n);
+      life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(n));
     }
     if (rec && stepped) {
       ems_step_record& r = rec[t.src];
@@ -1748,7 +1751,10 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     if (looped) agg_add(P, sh_agg, agg_key(kTagLedger + 1, e), fixed_point(t.T, sc));
     const int delta = (alive ? 1 : 0) + o.nsec - 1;
     if (delta) agg_add(P, sh_agg, agg_key(kTagAlive, e), (unsigned long long)(long long)delta);
-    if (!alive) life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(t.nstep));
+    if (!alive) {  // the track ends: its steps go to the event's track-steps once
+      if (t.nstep) agg_add(P, sh_agg, agg_key(kTagSteps, e * 3u + (uint32_t)t.sp), t.nstep);
+      life_add(sh_life, (uint32_t)t.sp * kLifeBins + life_bin(t.nstep));
+    }
     if (rec) {
       ems_step_record& r = rec[t.src];
       r.dep += o.dep;
