@@ -156,8 +156,8 @@ struct Params {
   const int* cand;
   uint32_t seed;
   // tallies (per event slot) and run counters
-  unsigned long long* tally;     // [slot][nbins], fixed point
-  unsigned long long* ledger;    // [slot][kLedger]
+  unsigned long long* tally;     // [slot][kEvCopies][nbins], fixed point
+  unsigned long long* ledger;    // [slot][kEvCopies][kLedger]
   int* alive;                    // [slot] tracks alive or queued
   const double* scale;           // [slot] fixed-point scale 2^s
   uint32_t* slot_state;          // [slot] 0 free, 1 in flight, 2 finished, 3 being read

@@ -1902,34 +1902,70 @@ __global__ void k_iter_begin(unsigned long long* ctr, int explicit_counts, uint3
 // Before the host reads the counters of a sync interval: an event in flight whose
 // alive copies sum to zero has no track left anywhere (pool, queues, host spill):
 // it is finished and can be read.
-__global__ void k_done_scan(Params P) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= P.max_events || P.slot_state[e] != 1u) return;
-  int a = 0;
+// Grid-stride over the slots, one count per block: one atomic per finished event
+// (one per wavefront, once merged) would queue on the counter's one address.
+__global__ __launch_bounds__(256) void k_done_scan(Params P) {
+  __shared__ uint32_t sh_n[256 / 64];
+  uint32_t done = 0;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < P.max_events;
+       e += gridDim.x * blockDim.x) {
+    if (P.slot_state[e] != 1u) continue;
+    int a = 0;
 #pragma unroll
-  for (int c = 0; c < kEvCopies; ++c) a += P.alive[(size_t)e * kEvCopies + c];
-  if (a == 0) {
-    P.slot_state[e] = 2u;
-    atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), 1u);
+    for (int c = 0; c < kEvCopies; ++c) a += P.alive[(size_t)e * kEvCopies + c];
+    if (a == 0) {
+      P.slot_state[e] = 2u;
+      ++done;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) done += __shfl_xor(done, off);
+  if ((threadIdx.x & 63) == 0) sh_n[threadIdx.x >> 6] = done;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = sh_n[0] + sh_n[1] + sh_n[2] + sh_n[3];
+    if (t) atomicAdd(reinterpret_cast<uint32_t*>(ctr_line(P, kLDone)), t);
   }
 }
 
 // Admit queued primaries: ring entries [head, head + m) appended to the photon or
 // charged pool at the admission cursors (one atomic per wavefront and class).
-__global__ void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur, uint32_t head, uint32_t m) {
+// Blocks of kAdmitBlock threads reserve their photon and charged rows with one
+// atomic on the admission cursors (a batch of 1e7 one-photon events would otherwise
+// queue 1.6e5 wavefront atomics on that one address).
+constexpr int kAdmitBlock = 1024;
+__global__ __launch_bounds__(kAdmitBlock) void k_admit(Params P, Queue q, Pool S, uint32_t N, int cur,
+                                                       uint32_t head, uint32_t m) {
+  constexpr int kW = kAdmitBlock / 64;
+  __shared__ uint32_t sh_g[kW], sh_c[kW];
+  __shared__ unsigned long long sh_old;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool valid = j < m;
   const uint32_t r = valid ? (head + j) % q.capacity : 0u;
   const int sp = valid ? q.species[r] : 0;
   const bool g = valid && sp == EMS_GAMMA, c = valid && sp != EMS_GAMMA;
   const uint64_t mg = __ballot(g), mc = __ballot(c);
-  unsigned long long old = 0;
-  if (lane == 0 && (mg | mc))
-    old = atomicAdd(ctr_line(P, kLAdmit),
-                    ((unsigned long long)__popcll(mc) << 32) | (unsigned long long)__popcll(mg));
-  old = __shfl(old, 0);
-  const uint32_t bg = lo32(old), bc = hi32(old);
+  if (lane == 0) {
+    sh_g[wave] = (uint32_t)__popcll(mg);
+    sh_c[wave] = (uint32_t)__popcll(mc);
+  }
+  __syncthreads();
+  uint32_t bg = 0, bc = 0, tg = 0, tc = 0;
+#pragma unroll
+  for (int w2 = 0; w2 < kW; ++w2) {
+    if (w2 < wave) {
+      bg += sh_g[w2];
+      bc += sh_c[w2];
+    }
+    tg += sh_g[w2];
+    tc += sh_c[w2];
+  }
+  if (threadIdx.x == 0)
+    sh_old = (tg | tc) ? atomicAdd(ctr_line(P, kLAdmit), ((unsigned long long)tc << 32) | tg) : 0ull;
+  __syncthreads();
+  bg += lo32(sh_old);
+  bc += hi32(sh_old);
   if (!valid) return;
   const double x = q.x[r], y = q.y[r], z = q.z[r], u = q.u[r], v = q.v[r], w = q.w[r];
   uint32_t a, b, cc, d;
@@ -2011,10 +2047,6 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
   const uint32_t slot = slots[e];
   if (slot >= P.max_events) return;  // a refused batch (no slot)
   P.slot_state[slot] = 1u;
-  for (int j = 0; j < kEvCopies * P.nbins; ++j) P.tally[(size_t)slot * kEvCopies * P.nbins + j] = 0ull;
-  for (int j = 0; j < kEvCopies * kLedger; ++j) P.ledger[(size_t)slot * kEvCopies * kLedger + j] = 0ull;
-  if (P.ev_esc)
-    for (int j = 0; j < 3 * kGrid; ++j) P.ev_esc[(size_t)slot * 3 * kGrid + j] = 0ull;
   int ex = 0;
   if (sm > 0.0) frexp(sm, &ex);  // E_max < 2^ex
   e_in[slot] = s;
@@ -2022,6 +2054,25 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
   scale[slot] = ldexp(1.0, 61 - ex);
   P.alive[(size_t)slot * kEvCopies] = (int)(b - a);
   for (int c = 1; c < kEvCopies; ++c) P.alive[(size_t)slot * kEvCopies + c] = 0;
+}
+
+// Zero the score rows (tally bins, ledger words and the optional escape spectrum, in
+// every copy) of a batch's event slots: consecutive threads write consecutive words
+// of a row, so the stores of slots that follow one another are coalesced.
+__device__ __forceinline__ void zero_rows(unsigned long long* base, const uint32_t* slots,
+                                          uint32_t n_events, uint32_t words, uint32_t max_events) {
+  const uint64_t total = (uint64_t)n_events * words;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = (uint32_t)(t / words), w = (uint32_t)(t - (uint64_t)e * words);
+    const uint32_t slot = slots[e];
+    if (slot < max_events) base[(size_t)slot * words + w] = 0ull;
+  }
+}
+__global__ void k_event_zero(Params P, const uint32_t* slots, uint32_t n_events) {
+  zero_rows(P.tally, slots, n_events, (uint32_t)(kEvCopies * P.nbins), P.max_events);
+  zero_rows(P.ledger, slots, n_events, (uint32_t)(kEvCopies * kLedger), P.max_events);
+  if (P.ev_esc) zero_rows(P.ev_esc, slots, n_events, (uint32_t)(3 * kGrid), P.max_events);
 }
 
 // ------------------------------------------------------------------ spilling to host memory
@@ -2266,7 +2317,8 @@ hipError_t launch_iteration(const Params& P, const Pool& S, uint32_t N, int cur,
 }
 
 hipError_t launch_done_scan(const Params& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_done_scan, dim3(blocks_for(P.max_events, 256)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_done_scan, dim3(std::min<uint32_t>(blocks_for(P.max_events, 256), 2048)), dim3(256),
+                     0, s, P);
   return hipGetLastError();
 }
 
@@ -2280,7 +2332,8 @@ hipError_t launch_iter_begin(unsigned long long* ctr, bool explicit_counts, uint
 hipError_t launch_admit(const Params& P, const Queue& q, const Pool& S, uint32_t N, int cur,
                         uint32_t head, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, 256)), dim3(256), 0, s, P, q, S, N, cur, head, m);
+  hipLaunchKernelGGL(k_admit, dim3(blocks_for(m, kAdmitBlock)), dim3(kAdmitBlock), 0, s, P, q, S, N, cur,
+                     head, m);
   return hipGetLastError();
 }
 
@@ -2301,6 +2354,11 @@ hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t
   if (n_events == 0) return hipSuccess;
   hipLaunchKernelGGL(k_event_init, dim3(blocks_for(n_events, 256)), dim3(256), 0, s, P, off, slots,
                      n_events, n, T, sp, e_in, scale, e_row, quarter, bad);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t words = (uint64_t)n_events * kEvCopies * (uint64_t)(P.nbins > kLedger ? P.nbins : kLedger);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_for(words, 256), 8192);
+  hipLaunchKernelGGL(k_event_zero, dim3(blocks), dim3(256), 0, s, P, slots, n_events);
   return hipGetLastError();
 }
 
