@@ -1623,7 +1623,7 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     Q.evt[j] = t.evt;
     Q.nstep[j] = t.nstep;
     Q.meta[j] = make_meta(t.sp, (uint32_t)t.vol);
-    Q.src[j] = t.src;
+    if (rec) Q.src[j] = t.src;  // the step record of its state (diagnostics only)
   }
 }
 
@@ -1723,7 +1723,7 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
     const uint32_t meta = Q.meta[j];
     t.sp = (int)(meta & 3u);
     t.vol = (int)((meta >> 6) & kVolMask);
-    t.src = Q.src[j];
+    t.src = rec ? Q.src[j] : 0u;
     t.nlam = -1.0;
     if (put_off) {
       alive = true;  // back to the pool unchanged, flagged with its queue
