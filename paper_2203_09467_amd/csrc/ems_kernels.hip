@@ -1391,10 +1391,9 @@ __device__ __forceinline__ View<R> stage_view(const Params& P, bool charged_clas
 
 // One iteration, part 1, for chunk c of kBlock tracks: chunks [0, nbG) of the
 // photon pool, then the charged pool (so every wavefront holds one species class).
-// In each pool the first k tracks are stepped and the rest copied unchanged
-// (deferred for lack of output room).  Survivors go to the output pool of their
-// class, tracks that interact to their process queue; both are reserved once per
-// block.
+// Every track takes up to msteps steps (a track whose interaction was put off
+// goes straight to its queue); survivors go to the output pool of their class,
+// tracks that interact to their process queue; both are reserved once per block.
 template <class R, bool FIELD, bool STAGED, bool CSG, bool MSC>
 __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, uint32_t N, int cur,
                                                 const IQueue& Q, ems_step_record* rec,
