@@ -81,6 +81,22 @@ def test_photon_cube_full_size(orc):
     _check_life(g, o)
 
 
+def test_photon_cube_many_events(orc):
+    """600 000 one-photon events in one batch: more event slots than one pass of the
+    completion scan's grid covers (2048 blocks of 256) and hundreds of admission
+    blocks.  Every event finishes, closes its energy, and a sample of them (the
+    oracle draws per event, so any subset is comparable) equals the oracle."""
+    wl = W.photon_cube(600_000)
+    g = _run_gpu(wl, wl.events, pool=1 << 22)
+    assert np.abs(_ledger_residual(g["dep"], g["ledger"])).max() < 1e-12
+    idx = np.arange(0, 600_000, 30)
+    sub = wl.events.subset(idx)
+    o = orc.World(wl.materials, wl.options, wl.geometry).run_events(wl.seed, sub)
+    e_in = o["ledger"][:, 0]
+    assert np.array_equal(g["ledger"][idx, 0], e_in)
+    assert _per_event_match(g["dep"][idx], o["dep"], e_in).mean() >= 0.99
+
+
 def _check_life(g, o):
     """Steps-per-track histogram: within what the events that differ can move, and
     consistent with the GPU's own step counts."""
