@@ -179,6 +179,7 @@ struct Params {
 struct EvSlots {
   uint32_t* bits;
   uint32_t* pre;      // words + 1 entries
+  uint32_t* tile;     // per tile of kFreeTile words: its free count, then its offset
   uint32_t words;     // ceil(n / 32)
   unsigned long long* map;
   uint32_t mask;

@@ -225,6 +225,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   ev.words = (uint32_t)((E + 31) / 32);
   ev.bits = c.take<uint32_t>(ev.words);
   ev.pre = c.take<uint32_t>((size_t)ev.words + 1);
+  ev.tile = c.take<uint32_t>((size_t)(ev.words + kFreeTile - 1) / kFreeTile + 1);
   ev.map = c.take<unsigned long long>(mcap);
   ev.mask = (uint32_t)(mcap - 1);
   ev.state = c.take<uint32_t>(E);

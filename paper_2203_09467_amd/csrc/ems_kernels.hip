@@ -2476,12 +2476,45 @@ struct DeviceCas {
 };
 
 // Submission, part 1 (one block): pre[w] = free slots in the bitmap words [0, w).
-__global__ __launch_bounds__(1024) void k_free_scan(EvSlots M) {
+// Submission, part 1: pre[w], the free slots in words [0, w), in three passes --
+// each tile of kFreeTile words (one block, 16 words per thread) counts within
+// itself and keeps its total, one block turns the totals into offsets, and every
+// word adds its tile's offset.
+__global__ __launch_bounds__(256) void k_free_tile(EvSlots M) {
+  constexpr uint32_t kPer = kFreeTile / 256u;
+  __shared__ uint32_t sh_w[4];
+  const uint32_t base = blockIdx.x * kFreeTile + threadIdx.x * kPer;
+  uint32_t c[kPer], sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    c[k] = base + k < M.words ? (uint32_t)__popc(M.bits[base + k]) : 0u;
+    sum += c[k];
+  }
+  // exclusive scan of the threads' sums: within the wavefront, then over wavefronts
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) sh_w[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int w2 = 0; w2 < wave; ++w2) run += sh_w[w2];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    if (base + k < M.words) M.pre[base + k] = run;
+    run += c[k];
+  }
+  if (threadIdx.x == 255) M.tile[blockIdx.x] = run;
+}
+__global__ __launch_bounds__(1024) void k_free_tiles(EvSlots M, uint32_t tiles) {
   __shared__ uint32_t part[1024];
-  const uint32_t t = threadIdx.x, per = (M.words + 1023u) / 1024u;
-  const uint32_t a = min(M.words, t * per), b = min(M.words, a + per);
+  const uint32_t t = threadIdx.x, per = (tiles + 1023u) / 1024u;
+  const uint32_t a = min(tiles, t * per), b = min(tiles, a + per);
   uint32_t c = 0;
-  for (uint32_t w = a; w < b; ++w) c += (uint32_t)__popc(M.bits[w]);
+  for (uint32_t j = a; j < b; ++j) c += M.tile[j];
   part[t] = c;
   __syncthreads();
   for (uint32_t off = 1; off < 1024u; off <<= 1) {  // inclusive scan of the parts
@@ -2491,11 +2524,16 @@ __global__ __launch_bounds__(1024) void k_free_scan(EvSlots M) {
     __syncthreads();
   }
   uint32_t run = part[t] - c;
-  for (uint32_t w = a; w < b; ++w) {
-    M.pre[w] = run;
-    run += (uint32_t)__popc(M.bits[w]);
+  for (uint32_t j = a; j < b; ++j) {
+    const uint32_t v = M.tile[j];
+    M.tile[j] = run;
+    run += v;
   }
   if (t == 1023u) M.pre[M.words] = part[t];
+}
+__global__ void k_free_add(EvSlots M) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < M.words && w >= kFreeTile) M.pre[w] += M.tile[w / kFreeTile];
 }
 
 // Submission, part 2: event e of the batch takes the free slot of rank e -- a batch
@@ -2522,9 +2560,23 @@ __global__ void k_slots_take(EvSlots M, const uint32_t* ids, uint32_t n, uint32_
 }
 
 // Submission, part 3 (after part 2 has read the bitmap): the taken slots leave it.
+// A batch's slots rise with its event index (kNoSlot, if any, last), so lanes whose
+// slots share a bitmap word are adjacent: each lane gathers the bits of the lanes
+// after it in its run, and the run's first lane clears them with one atomic.
 __global__ void k_slots_mark(EvSlots M, const uint32_t* slots, uint32_t n) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n && slots[e] != kNoSlot) atomicAnd(&M.bits[slots[e] >> 5], ~(1u << (slots[e] & 31u)));
+  const uint32_t sl = e < n ? slots[e] : kNoSlot;
+  const bool ok = sl != kNoSlot;
+  const uint32_t w = ok ? sl >> 5 : 0xFFFFFFFFu;
+  uint32_t m = ok ? 1u << (sl & 31u) : 0u;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t w2 = __shfl_down(w, off), m2 = __shfl_down(m, off);
+    if (lane + off < 64 && w2 == w) m |= m2;
+  }
+  const uint32_t wp = __shfl_up(w, 1);
+  if (ok && (lane == 0 || wp != w)) atomicAnd(&M.bits[w], ~m);
 }
 
 // A rejected batch: its entries are erased and its slots are free again.
@@ -2620,7 +2672,10 @@ hipError_t launch_gather_tallies(const Params& P, const uint32_t* slots, uint32_
 hipError_t launch_slots_take(const EvSlots& M, const uint32_t* ids, uint32_t n, uint32_t* slots,
                              uint32_t* flag, unsigned long long* bad, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_free_scan, dim3(1), dim3(1024), 0, s, M);
+  const uint32_t tiles = (M.words + kFreeTile - 1) / kFreeTile;
+  hipLaunchKernelGGL(k_free_tile, dim3(tiles), dim3(256), 0, s, M);
+  hipLaunchKernelGGL(k_free_tiles, dim3(1), dim3(1024), 0, s, M, tiles);
+  if (tiles > 1) hipLaunchKernelGGL(k_free_add, dim3(blocks_for(M.words, 256)), dim3(256), 0, s, M);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slots_take, dim3(blocks_for(n, 256)), dim3(256), 0, s, M, ids, n, slots, flag,

@@ -79,6 +79,9 @@ EMS_HD inline void map_erase(unsigned long long* map, uint32_t mask, uint32_t id
 // Free slots are the set bits of a bitmap; pre[w] counts the set bits of words
 // [0, w).  The free slot of rank r (0-based, in increasing slot order) is in the
 // word w with pre[w] <= r < pre[w + 1], at the bit of rank r - pre[w] within it.
+// The device computes pre per tile of kFreeTile words, then adds the tiles'
+// offsets.
+constexpr uint32_t kFreeTile = 4096;
 
 // Index (0..31) of the set bit of rank r in x (r < popcount(x)): binary descent on
 // the popcounts of the low halves.
