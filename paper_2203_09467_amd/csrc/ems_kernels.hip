@@ -2056,16 +2056,20 @@ __global__ void k_event_init(Params P, const int64_t* off, const uint32_t* slots
 }
 
 // Zero the score rows (tally bins, ledger words and the optional escape spectrum, in
-// every copy) of a batch's event slots: consecutive threads write consecutive words
-// of a row, so the stores of slots that follow one another are coalesced.
+// every copy) of a batch's event slots, 16 bytes per store: consecutive threads
+// write consecutive parts of a row, so the stores of slots that follow one another
+// are coalesced.  A row is a multiple of 16 bytes (kEvCopies or 3 * kGrid words),
+// and a batch's 16-byte parts number below 2^31 (the score indices of the event
+// slots fit 28 bits; the ledger has 32 parts per slot and at most 2^26 slots).
+static_assert(kEvCopies % 2 == 0 && (3 * kGrid) % 2 == 0, "score rows are whole 16-byte parts");
 __device__ __forceinline__ void zero_rows(unsigned long long* base, const uint32_t* slots,
                                           uint32_t n_events, uint32_t words, uint32_t max_events) {
-  const uint64_t total = (uint64_t)n_events * words;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = (uint32_t)(t / words), w = (uint32_t)(t - (uint64_t)e * words);
+  uint4* const b16 = reinterpret_cast<uint4*>(base);
+  const uint32_t row = words / 2u, total = n_events * row;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const uint32_t e = t / row, w = t - e * row;
     const uint32_t slot = slots[e];
-    if (slot < max_events) base[(size_t)slot * words + w] = 0ull;
+    if (slot < max_events) b16[(size_t)slot * row + w] = make_uint4(0u, 0u, 0u, 0u);
   }
 }
 __global__ void k_event_zero(Params P, const uint32_t* slots, uint32_t n_events) {
@@ -2355,7 +2359,7 @@ hipError_t launch_event_init(const Params& P, const int64_t* off, const uint32_t
                      n_events, n, T, sp, e_in, scale, e_row, quarter, bad);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const uint64_t words = (uint64_t)n_events * kEvCopies * (uint64_t)(P.nbins > kLedger ? P.nbins : kLedger);
+  const uint64_t words = (uint64_t)n_events * (kEvCopies / 2) * (uint64_t)(P.nbins > kLedger ? P.nbins : kLedger);
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_for(words, 256), 8192);
   hipLaunchKernelGGL(k_event_zero, dim3(blocks), dim3(256), 0, s, P, slots, n_events);
   return hipGetLastError();
