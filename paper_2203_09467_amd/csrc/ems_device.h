@@ -65,8 +65,8 @@ enum QueueId {
 };
 
 struct IQueue {
-  double *x, *y, *z, *u, *v, *w, *T;
-  uint32_t *k0, *k1, *k2, *evt, *nstep, *meta, *src;
+  uint4* rec;  // 5 x 16 B per entry: (x, y) (z, u) (v, w) (T, k0 k1) (k2 evt nstep meta)
+  uint32_t* src;
   uint32_t capacity;  // per queue; queue q occupies [q * capacity, (q + 1) * capacity)
 };
 

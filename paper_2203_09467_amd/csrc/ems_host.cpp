@@ -157,19 +157,7 @@ void carve(Carver& c, const ems_config& cfg, ems_ctx* x) {
   set.ftrav = c.take<double>(4 * N);
   IQueue iq;
   const size_t NQ = (size_t)kNumQueues * N;
-  iq.x = c.take<double>(NQ);
-  iq.y = c.take<double>(NQ);
-  iq.z = c.take<double>(NQ);
-  iq.u = c.take<double>(NQ);
-  iq.v = c.take<double>(NQ);
-  iq.w = c.take<double>(NQ);
-  iq.T = c.take<double>(NQ);
-  iq.k0 = c.take<uint32_t>(NQ);
-  iq.k1 = c.take<uint32_t>(NQ);
-  iq.k2 = c.take<uint32_t>(NQ);
-  iq.evt = c.take<uint32_t>(NQ);
-  iq.nstep = c.take<uint32_t>(NQ);
-  iq.meta = c.take<uint32_t>(NQ);
+  iq.rec = c.take<uint4>(NQ * 5);
   iq.src = c.take<uint32_t>(NQ);
   iq.capacity = (uint32_t)N;
   double* tab_d = c.take<double>((size_t)kMaxMat * 3 * kGrid * kQ);

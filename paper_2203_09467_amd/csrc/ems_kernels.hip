@@ -1609,19 +1609,13 @@ __device__ __forceinline__ void transport_chunk(const Params& P, const Pool& S, 
     uint32_t j = sh_base[1 + q] + lanes_below(own, lane);
     for (int w2 = 0; w2 < wave; ++w2) j += sh_cnt[w2][1 + q];
     j += (uint32_t)q * Q.capacity;
-    Q.x[j] = t.x;
-    Q.y[j] = t.y;
-    Q.z[j] = t.z;
-    Q.u[j] = t.u;
-    Q.v[j] = t.v;
-    Q.w[j] = t.w;
-    Q.T[j] = t.T;
-    Q.k0[j] = t.k0;
-    Q.k1[j] = t.k1;
-    Q.k2[j] = t.k2;
-    Q.evt[j] = t.evt;
-    Q.nstep[j] = t.nstep;
-    Q.meta[j] = make_meta(t.sp, (uint32_t)t.vol);
+    uint4* qe = Q.rec + (size_t)j * 5;
+    const unsigned long long Tb = (unsigned long long)__double_as_longlong(t.T);
+    reinterpret_cast<double2*>(qe)[0] = make_double2(t.x, t.y);
+    reinterpret_cast<double2*>(qe)[1] = make_double2(t.z, t.u);
+    reinterpret_cast<double2*>(qe)[2] = make_double2(t.v, t.w);
+    qe[3] = make_uint4((uint32_t)Tb, (uint32_t)(Tb >> 32), t.k0, t.k1);
+    qe[4] = make_uint4(t.k2, t.evt, t.nstep, make_meta(t.sp, (uint32_t)t.vol));
     if (rec) Q.src[j] = t.src;  // the step record of its state (diagnostics only)
   }
 }
@@ -1707,19 +1701,24 @@ __device__ __forceinline__ void interact_chunk(const Params& P, const IQueue& Q,
   bool alive = false, looped = false;
   if (valid) {
     const uint32_t j = q * Q.capacity + i;
-    t.x = Q.x[j];
-    t.y = Q.y[j];
-    t.z = Q.z[j];
-    t.u = Q.u[j];
-    t.v = Q.v[j];
-    t.w = Q.w[j];
-    t.T = Q.T[j];
-    t.k0 = Q.k0[j];
-    t.k1 = Q.k1[j];
-    t.k2 = Q.k2[j];
-    t.evt = Q.evt[j];
-    t.nstep = Q.nstep[j];
-    const uint32_t meta = Q.meta[j];
+    const uint4* qe = Q.rec + (size_t)j * 5;
+    const double2 a0 = reinterpret_cast<const double2*>(qe)[0];
+    const double2 a1 = reinterpret_cast<const double2*>(qe)[1];
+    const double2 a2 = reinterpret_cast<const double2*>(qe)[2];
+    const uint4 a3 = qe[3], a4 = qe[4];
+    t.x = a0.x;
+    t.y = a0.y;
+    t.z = a1.x;
+    t.u = a1.y;
+    t.v = a2.x;
+    t.w = a2.y;
+    t.T = __longlong_as_double((long long)(((unsigned long long)a3.y << 32) | a3.x));
+    t.k0 = a3.z;
+    t.k1 = a3.w;
+    t.k2 = a4.x;
+    t.evt = a4.y;
+    t.nstep = a4.z;
+    const uint32_t meta = a4.w;
     t.sp = (int)(meta & 3u);
     t.vol = (int)((meta >> 6) & kVolMask);
     t.src = rec ? Q.src[j] : 0u;
